@@ -1,0 +1,217 @@
+"""Pins for the CPU oracle against things fixed by mathematics, not by the
+oracle itself: closed forms, a textbook Cholesky, LAPACK's QR as an
+independent library routine, the invariants, and special cases.
+
+Each test is chosen so that a plausible slip in oracle.c (a dropped term, a
+wrong sign, a wrong index, a transposed operand, a wrong order of the
+reflectors) fails at least one of them.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1102_5328_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "qr_closed_forms.txt")
+
+
+def _read_golden():
+    cases, cur = {}, None
+    for line in open(GOLDEN):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        key, val = line.split("=", 1)
+        if key == "name":
+            cur = cases.setdefault(val, {})
+            continue
+        rows = [[float(x) for x in r.split()] for r in val.split(";")]
+        cur[key] = np.array(rows if len(rows) > 1 else rows[0])
+    return cases
+
+
+def test_2x2_closed_form(orc):
+    g = _read_golden()["2x2"]
+    VR, tau = orc.geqr2(g["A"])
+    np.testing.assert_allclose(orc.upper(VR), g["R"], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(tau, g["tau"], rtol=0, atol=1e-15)
+    np.testing.assert_allclose([1.0, VR[1, 0]], g["v0"], rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_2x2_general_formula(orc, seed):
+    rng = np.random.default_rng(100 + seed)
+    a, b, c, d = rng.standard_normal(4)
+    if seed == 0:
+        a = 0.0  # sign(0) = +1 -> beta negative
+    beta = -(1.0 if a >= 0 else -1.0) * np.hypot(a, c)
+    R = np.array([[beta, (a * b + c * d) / beta], [0.0, -(a * d - b * c) / beta]])
+    VR, tau = orc.geqr2(np.array([[a, b], [c, d]]))
+    np.testing.assert_allclose(orc.upper(VR), R, rtol=1e-13, atol=1e-14)
+    np.testing.assert_allclose(tau[0], (beta - a) / beta, rtol=1e-14)
+
+
+def test_3x3_constructed(orc):
+    g = _read_golden()["3x3"]
+    VR, tau = orc.geqr2(g["A"])
+    np.testing.assert_allclose(orc.sign_normalize(orc.upper(VR)), g["Rnorm"],
+                               rtol=0, atol=1e-13)
+    np.testing.assert_allclose(tau[0], g["tau0"], rtol=1e-15)
+    np.testing.assert_allclose([1.0, VR[1, 0], VR[2, 0]], g["v0"], rtol=0, atol=1e-15)
+
+
+def _cholesky_textbook(S):
+    """Cholesky-Banachiewicz, written out; S = L L^T, returns U = L^T."""
+    n = S.shape[0]
+    L = np.zeros_like(S)
+    for i in range(n):
+        for j in range(i + 1):
+            s = S[i, j] - sum(L[i, k] * L[j, k] for k in range(j))
+            L[i, j] = np.sqrt(s) if i == j else s / L[j, j]
+    return L.T
+
+
+@pytest.mark.parametrize("shape", [(12, 7), (9, 9), (30, 5)])
+def test_R_is_cholesky_of_gram(orc, shape):
+    A = inputs.uniform(*shape, seed=3)
+    assert np.linalg.cond(A) < 1e3
+    VR, _ = orc.geqr2(A)
+    R = orc.sign_normalize(orc.upper(VR))
+    U = _cholesky_textbook(A.T @ A)
+    np.testing.assert_allclose(R, U, rtol=1e-11, atol=1e-12)
+
+
+@pytest.mark.parametrize("shape", [(64, 64), (200, 37), (37, 200), (1, 5), (5, 1), (1, 1)])
+def test_matches_lapack_qr(orc, shape):
+    A = inputs.normal(*shape, seed=7)
+    VR, tau = orc.geqr2(A)
+    R_lapack = np.linalg.qr(A, mode="r")
+    assert orc.r_rel_diff(orc.upper(VR), R_lapack) < 1e-13
+
+
+@pytest.mark.parametrize("shape", [(96, 96), (150, 60), (60, 150), (257, 129)])
+def test_invariants(orc, shape):
+    M, N = shape
+    A = inputs.uniform(M, N, seed=11)
+    VR, tau = orc.geqr2(A)
+    Q = orc.form_q(VR, tau)
+    R = orc.upper(VR)
+    bound = orc.invariant_bound(M, N)
+    assert orc.residual(A, Q, R) <= bound
+    assert orc.orthogonality(Q) <= bound
+    # Q^T A is upper triangular: the reflectors annihilate below the diagonal.
+    QtA = orc.apply_qt(VR, tau, A)
+    low = np.tril(QtA, -1)
+    assert np.linalg.norm(low) <= bound * np.linalg.norm(A)
+    np.testing.assert_allclose(np.triu(QtA)[:min(M, N)], R, atol=bound * np.linalg.norm(A))
+
+
+def test_qt_then_q_is_identity(orc):
+    A = inputs.normal(80, 50, seed=2)
+    VR, tau = orc.geqr2(A)
+    B = inputs.normal(80, 13, seed=4)
+    back = orc.apply_q(VR, tau, orc.apply_qt(VR, tau, B))
+    np.testing.assert_allclose(back, B, atol=1e-13)
+
+
+def test_upper_triangular_input_is_fixed_point(orc):
+    """Columns already zero below the diagonal: tau = 0, R = A (signs kept)."""
+    A = np.triu(inputs.normal(6, 6, seed=5))
+    VR, tau = orc.geqr2(A)
+    assert np.all(tau == 0.0)
+    np.testing.assert_array_equal(orc.upper(VR), A)
+
+
+def test_zero_column_and_rank_deficiency(orc):
+    A = inputs.normal(10, 4, seed=6)
+    A[:, 1] = 0.0
+    A[:, 3] = A[:, 0] * 2.0
+    VR, tau = orc.geqr2(A)
+    R = orc.upper(VR)
+    assert R[1, 1] == 0.0 and tau[1] == 0.0
+    assert abs(R[3, 3]) < 1e-14
+    Q = orc.form_q(VR, tau)
+    assert orc.residual(A, Q, R) < 1e-14
+
+
+def test_single_column_is_norm(orc):
+    a = inputs.normal(33, 1, seed=8)
+    VR, tau = orc.geqr2(a)
+    assert VR[0, 0] == pytest.approx(-np.sign(a[0, 0]) * np.linalg.norm(a), rel=1e-15)
+
+
+def test_compact_wy_T_matches_product_of_reflectors(orc):
+    """I - V T V^T equals H_{j0} ... H_{j0+k-1}, each applied on its own."""
+    M, N = 40, 24
+    A = inputs.normal(M, N, seed=9)
+    VR, tau = orc.geqr2(A)
+    for j0, k in [(0, 8), (8, 16), (3, 5), (0, 24)]:
+        T = orc.larft(VR, tau, j0, k)
+        assert np.allclose(np.tril(T, -1), 0.0)
+        np.testing.assert_allclose(np.diag(T), tau[j0:j0 + k])
+        V = np.zeros((M, k))
+        for c in range(k):
+            j = j0 + c
+            V[j, c] = 1.0
+            V[j + 1:, c] = VR[j + 1:, j]
+        # Product H_{j0} ... H_{j0+k-1} = apply the reflectors j0+k-1 .. j0 to I.
+        tt = np.zeros(j0 + k)
+        tt[j0:] = tau[j0:j0 + k]
+        Hprod = orc.apply_q(VR[:, :j0 + k], tt, np.eye(M))
+        np.testing.assert_allclose(np.eye(M) - V @ T @ V.T, Hprod, atol=1e-14)
+
+
+def test_gram_entry(orc):
+    A = inputs.normal(50, 6, seed=12)
+    assert orc.gram_entry(A, 2, 4) == pytest.approx(float(A[:, 2] @ A[:, 4]), rel=1e-14)
+
+
+def test_tall_ragged_tile_stack_special_case(orc):
+    """QR of [R; A2] with R upper triangular: every reflector is zero in the
+    rows of R below its own diagonal entry (the DTSQRT structure)."""
+    b, mb = 12, 9
+    R = np.triu(inputs.normal(b, b, seed=13))
+    A2 = inputs.normal(mb, b, seed=14)
+    VR, tau = orc.geqr2(np.vstack([R, A2]))
+    for j in range(b):
+        np.testing.assert_array_equal(VR[j + 1:b, j], 0.0)
+    # [R; 0] is already triangular: nothing to do.
+    VR0, tau0 = orc.geqr2(np.vstack([R, np.zeros((mb, b))]))
+    assert np.all(tau0 == 0.0)
+    np.testing.assert_array_equal(orc.upper(VR0), R)
+
+
+def test_mlp_grad_matches_finite_differences(orc):
+    rng = np.random.default_rng(0)
+    p = rng.standard_normal(orc.MLP_NPARAM) * 0.3
+    X = rng.standard_normal((7, 5))
+    y = rng.standard_normal(7)
+    loss, g = orc.mlp_grad(p, X, y)
+    yhat = orc.mlp_forward(p, X)
+    assert loss == pytest.approx(0.5 * np.mean((yhat - y) ** 2), rel=1e-13)
+    idx = rng.choice(orc.MLP_NPARAM, size=60, replace=False)
+    idx = np.concatenate([idx, [0, 319, 320, 383, 384, 4479, 4480, 4543, 4544,
+                                8639, 8640, 8703, 8704, 8767, 8768]])
+    h = 1e-6
+    for i in idx:
+        pp, pm = p.copy(), p.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (orc.mlp_grad(pp, X, y)[0] - orc.mlp_grad(pm, X, y)[0]) / (2 * h)
+        assert g[i] == pytest.approx(fd, rel=1e-5, abs=1e-8), i
+
+
+def test_mlp_forward_hand_computed(orc):
+    """A network with a single active path computes a hand-checkable value."""
+    p = np.zeros(orc.MLP_NPARAM)
+    p[0] = 2.0           # W1[0][0]
+    p[320] = 1.0         # b1[0]
+    p[384] = 3.0         # W2[0][0]
+    p[4544] = -1.0       # W3[0][0]
+    p[8640] = 10.0       # b3[0]
+    p[8704] = 0.5        # W4[0]
+    p[8768] = 0.25       # b4
+    X = np.array([[1.0, 0, 0, 0, 0], [-4.0, 0, 0, 0, 0]])
+    # x=1: h1=3, h2=9, h3=relu(-9+10)=1, y=0.75 ; x=-4: h1=relu(-7)=0 -> h3=10, y=5.25
+    np.testing.assert_allclose(orc.mlp_forward(p, X), [0.75, 5.25])
