@@ -1,1 +1,167 @@
-"""MI355X-native tile Householder QR with an empirical (NB, IB) autotuner."""
+"""MI355X-native tile Householder QR (FP64) with an empirical (NB, IB)
+autotuner and a learned cost model.
+
+The compute path is libtileqr.so (HIP kernels for gfx950 behind a C ABI,
+include/tileqr.h); this package marshals torch tensors into it. PyTorch only
+provides device memory and streams.
+
+Matrices are column-major: an M x N matrix is a torch tensor with
+stride(0) == 1 and stride(1) == lda >= M, e.g. ``colmajor(M, N)``.
+"""
+import ctypes
+
+from . import _lib
+from ._lib import TileQRError, check
+
+__all__ = [
+    "colmajor", "T_size", "factor", "apply_Qt", "factor_batched", "factor_loop", "sync",
+    "tile_task", "ssrfb_bench", "tune", "tune_load", "flops", "flops_executed", "dag_counts",
+    "plan_check", "plan_tasks", "TileQRError", "check",
+]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ld(t):
+    if t.dim() != 2 or t.stride(0) != 1:
+        raise ValueError("expected a column-major 2-D tensor (stride(0) == 1)")
+    return max(1, t.stride(1)) if t.shape[1] > 1 else max(1, t.shape[0])
+
+
+def colmajor(M, N, dtype=None, device="cuda", fill=None):
+    """An M x N column-major tensor (lda = M)."""
+    torch = _torch()
+    dtype = dtype or torch.float64
+    t = torch.empty((N, max(M, 1)), dtype=dtype, device=device).t()[:M]
+    if fill is not None:
+        t.fill_(fill)
+    return t
+
+
+def T_size(M, N, nb, ib):
+    n = _lib.lib().qr_T_size(M, N, nb, ib)
+    if n < 0:
+        raise TileQRError("qr_T_size: invalid argument %d" % -n)
+    return n
+
+
+def tune(M, N, batch=1):
+    nb, ib, src = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    check(_lib.lib().qr_tune(M, N, batch, ctypes.byref(nb), ctypes.byref(ib), ctypes.byref(src)), "qr_tune")
+    return nb.value, ib.value, src.value
+
+
+def tune_load(path):
+    check(_lib.lib().qr_tune_load(path.encode()), "qr_tune_load")
+
+
+def factor(A, nb=0, ib=0, T=None, stream=None):
+    """In-place tile QR of the column-major FP64 tensor A. Returns (A, T, nb, ib)."""
+    torch = _torch()
+    M, N = A.shape
+    if nb == 0 or ib == 0:
+        tnb, tib, _ = tune(M, N, 1)
+        nb = nb or tnb
+        ib = ib or min(tib, nb)
+    if T is None:
+        T = torch.empty(max(1, T_size(M, N, nb, ib)), dtype=torch.float64, device=A.device)
+    check(_lib.lib().qr_factor(ctypes.c_void_p(A.data_ptr()), M, N, _ld(A), nb, ib,
+                               ctypes.c_void_p(T.data_ptr()), _stream(stream)), "qr_factor")
+    return A, T, nb, ib
+
+
+def apply_Qt(A, T, nb, ib, B, stream=None):
+    """B <- Q^T B in place (B column-major, M rows)."""
+    M, N = A.shape
+    check(_lib.lib().qr_apply_Qt(ctypes.c_void_p(A.data_ptr()), M, N, _ld(A), nb, ib,
+                                 ctypes.c_void_p(T.data_ptr()), ctypes.c_void_p(B.data_ptr()),
+                                 B.shape[1], _ld(B), _stream(stream)), "qr_apply_Qt")
+    return B
+
+
+def _batch_args(As, nbs, ibs, Ts):
+    n = len(As)
+    P = ctypes.c_void_p * n
+    I64 = ctypes.c_int64 * n
+    INT = ctypes.c_int * n
+    a = P(*[ctypes.c_void_p(x.data_ptr()) for x in As])
+    m = I64(*[x.shape[0] for x in As])
+    nn = I64(*[x.shape[1] for x in As])
+    ld = I64(*[_ld(x) for x in As])
+    t = P(*[ctypes.c_void_p(x.data_ptr()) for x in Ts])
+    return a, m, nn, ld, INT(*nbs), INT(*ibs), t
+
+
+def factor_batched(As, nbs, ibs, Ts, stream=None):
+    """One persistent, graph-captured launch over all matrices."""
+    a, m, n, ld, nb, ib, t = _batch_args(As, nbs, ibs, Ts)
+    check(_lib.lib().qr_factor_batched(ctypes.cast(a, ctypes.c_void_p), m, n, ld, len(As), nb, ib,
+                                       ctypes.cast(t, ctypes.c_void_p), _stream(stream)),
+          "qr_factor_batched")
+
+
+def factor_loop(As, nbs, ibs, Ts, stream=None):
+    """One qr_factor launch per matrix (the baseline of the batched launch)."""
+    a, m, n, ld, nb, ib, t = _batch_args(As, nbs, ibs, Ts)
+    check(_lib.lib().qr_factor_loop(ctypes.cast(a, ctypes.c_void_p), m, n, ld, len(As), nb, ib,
+                                    ctypes.cast(t, ctypes.c_void_p), _stream(stream)),
+          "qr_factor_loop")
+
+
+def sync(stream=None):
+    check(_lib.lib().qr_sync(_stream(stream)), "qr_sync")
+
+
+def tile_task(kind, A, nb, ib, T, i, j, k, stream=None):
+    M, N = A.shape
+    check(_lib.lib().qr_tile_task(kind, ctypes.c_void_p(A.data_ptr()), M, N, _ld(A), nb, ib,
+                                  ctypes.c_void_p(T.data_ptr()), i, j, k, _stream(stream)),
+          "qr_tile_task")
+
+
+def ssrfb_bench(nb, ib, calls=50, workers=0):
+    sec = ctypes.c_double()
+    check(_lib.lib().qr_ssrfb_bench(nb, ib, calls, workers, ctypes.byref(sec)), "qr_ssrfb_bench")
+    return sec.value
+
+
+def flops(M, N):
+    return _lib.lib().qr_flops(M, N)
+
+
+def flops_executed(M, N, nb, ib):
+    return _lib.lib().qr_flops_executed(M, N, nb, ib)
+
+
+def dag_counts(M, N, nb):
+    c = (ctypes.c_int64 * 4)()
+    check(_lib.lib().qr_dag_counts(M, N, nb, c), "qr_dag_counts")
+    return list(c)
+
+
+def plan_check(M, N, nb, ib, nrhs=0, apply=False, workers=256, seed=0):
+    nt, seq, stress = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    check(_lib.lib().qr_plan_check(M, N, nb, ib, nrhs, int(apply), workers, seed, ctypes.byref(nt),
+                                   ctypes.byref(seq), ctypes.byref(stress)), "qr_plan_check")
+    return nt.value, seq.value, stress.value
+
+
+def plan_tasks(M, N, nb, ib, nrhs=0, apply=False, workers=256):
+    import numpy as np
+    nt = ctypes.c_int64()
+    check(_lib.lib().qr_plan_tasks(M, N, nb, ib, nrhs, int(apply), workers, None, 0, ctypes.byref(nt)),
+          "qr_plan_tasks")
+    out = np.zeros((max(1, nt.value), 5), dtype=np.int32)
+    check(_lib.lib().qr_plan_tasks(M, N, nb, ib, nrhs, int(apply), workers,
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), nt.value,
+                                   ctypes.byref(nt)), "qr_plan_tasks")
+    return out[:nt.value]

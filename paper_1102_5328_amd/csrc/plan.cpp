@@ -1,0 +1,410 @@
+// Host construction of the tile QR DAG and its ticket order.
+#include "plan.h"
+
+#include <algorithm>
+#include <cstring>
+#include <queue>
+#include <random>
+#include <unordered_map>
+
+void md_init(MatDesc &md, int64_t M, int64_t N, int nb, int ib, int w, int64_t nrhs) {
+  md.M = (int32_t)M;
+  md.N = (int32_t)N;
+  md.nb = nb;
+  md.ib = ib;
+  md.w = w;
+  md.MT = (int32_t)((M + nb - 1) / nb);
+  md.NT = (int32_t)((N + nb - 1) / nb);
+  md.KT = md.MT < md.NT ? md.MT : md.NT;
+  md.S = (nb + w - 1) / w;
+  md.nrhs = (int32_t)nrhs;
+  md.SB = nrhs > 0 ? (int32_t)((nrhs + w - 1) / w) : 0;
+  md.pad = 0;
+}
+
+void enum_factor_tasks(const MatDesc &md, int mat, std::vector<Task> &out) {
+  for (int k = 0; k < md.KT; ++k) {
+    out.push_back(make_task(TK_GEQRT, mat, k, k, k, 0));
+    for (int i = k + 1; i < md.MT; ++i) out.push_back(make_task(TK_TSQRT, mat, i, k, k, 0));
+    for (int j = k + 1; j < md.NT; ++j)
+      for (int s = 0; s < strips_of(md, j); ++s)
+        out.push_back(make_task(TK_LARFB, mat, k, j, k, s));
+    for (int i = k + 1; i < md.MT; ++i)
+      for (int j = k + 1; j < md.NT; ++j)
+        for (int s = 0; s < strips_of(md, j); ++s)
+          out.push_back(make_task(TK_SSRFB, mat, i, j, k, s));
+  }
+}
+
+void enum_apply_tasks(const MatDesc &md, int mat, std::vector<Task> &out) {
+  for (int k = 0; k < md.KT; ++k) {
+    for (int s = 0; s < md.SB; ++s) out.push_back(make_task(TK_LARFB_B, mat, k, 0, k, s));
+    for (int i = k + 1; i < md.MT; ++i)
+      for (int s = 0; s < md.SB; ++s) out.push_back(make_task(TK_SSRFB_B, mat, i, 0, k, s));
+  }
+}
+
+void dag_tile_counts(int64_t M, int64_t N, int nb, int64_t counts[4]) {
+  int64_t MT = (M + nb - 1) / nb, NT = (N + nb - 1) / nb, KT = MT < NT ? MT : NT;
+  counts[0] = KT;
+  counts[1] = counts[2] = counts[3] = 0;
+  for (int64_t k = 0; k < KT; ++k) {
+    counts[1] += MT - 1 - k;
+    counts[2] += NT - 1 - k;
+    counts[3] += (MT - 1 - k) * (NT - 1 - k);
+  }
+}
+
+double task_cost(const Task &t, const MatDesc &m) {
+  // Rough per-workgroup rates (ns units); only the relative sizes matter.
+  const double upd_rate = 120.0;   // flop/ns of one workgroup on LARFB/SSRFB
+  const double pan_rate = 60.0;    // flop/ns of the panel's blocked updates
+  const double col_lat = 1200.0;   // ns per Householder column in a panel
+  int s = task_strip(t);
+  switch (task_type(t)) {
+    case TK_GEQRT: {
+      double mb = tile_rows(m, t.k), nb = tile_cols(m, t.k);
+      double kk = mb < nb ? mb : nb;
+      return kk * col_lat + 2.0 * mb * nb * kk / pan_rate;
+    }
+    case TK_TSQRT: {
+      double mb = tile_rows(m, t.i), nb = tile_cols(m, t.k);
+      return nb * col_lat + 2.0 * mb * nb * nb / pan_rate;
+    }
+    case TK_LARFB: {
+      double mb = tile_rows(m, t.k), nb = tile_cols(m, t.k);
+      double c = tile_cols(m, t.j) - s * m.w;
+      c = c < m.w ? c : m.w;
+      return 2000.0 + 2.0 * mb * nb * c / upd_rate;
+    }
+    case TK_SSRFB: {
+      double mb = tile_rows(m, t.i), nb = tile_cols(m, t.k);
+      double c = tile_cols(m, t.j) - s * m.w;
+      c = c < m.w ? c : m.w;
+      return 2000.0 + 4.0 * mb * nb * c / upd_rate;
+    }
+    case TK_LARFB_B: {
+      double mb = tile_rows(m, t.k), nb = tile_cols(m, t.k);
+      double c = m.nrhs - s * m.w;
+      c = c < m.w ? c : m.w;
+      return 2000.0 + 2.0 * mb * nb * c / upd_rate;
+    }
+    case TK_SSRFB_B: {
+      double mb = tile_rows(m, t.i), nb = tile_cols(m, t.k);
+      double c = m.nrhs - s * m.w;
+      c = c < m.w ? c : m.w;
+      return 2000.0 + 4.0 * mb * nb * c / upd_rate;
+    }
+  }
+  return 1.0;
+}
+
+namespace {
+
+struct Dag {
+  std::vector<Task> tasks;          // program order
+  std::vector<int32_t> succ_off;    // CSR successors
+  std::vector<int32_t> succ;
+  std::vector<int32_t> ndeps;
+};
+
+// Derives the DAG edges from the counter protocol itself: the task a wait
+// (counter c, target v) depends on is the one that gives counter c its v-th
+// increment in program order.
+int derive_dag(const std::vector<MatDesc> &mats, bool apply, Dag &d) {
+  d.tasks.clear();
+  for (size_t m = 0; m < mats.size(); ++m) {
+    if (apply) enum_apply_tasks(mats[m], (int)m, d.tasks);
+    else enum_factor_tasks(mats[m], (int)m, d.tasks);
+  }
+  const int64_t T = (int64_t)d.tasks.size();
+  int64_t nctr = 0;
+  for (const MatDesc &m : mats) {
+    int64_t e = m.ctr + (apply ? ctr_count_apply(m) : ctr_count_factor(m));
+    nctr = e > nctr ? e : nctr;
+  }
+  std::vector<std::vector<int32_t>> signalers((size_t)nctr);
+  std::vector<int32_t> pred_off(T + 1, 0);
+  std::vector<int32_t> pred;
+  pred.reserve((size_t)T * 3);
+  for (int64_t t = 0; t < T; ++t) {
+    const Task &tk = d.tasks[t];
+    const MatDesc &m = mats[task_mat(tk)];
+    int nw = task_nwaits(tk, m);
+    for (int q = 0; q < nw; ++q) {
+      int64_t idx;
+      int target;
+      task_wait(tk, m, q, &idx, &target);
+      if (target <= 0) continue;
+      if (idx < 0 || idx >= nctr) return -2;
+      if ((int)signalers[idx].size() < target) return -3;  // would wait on a later task
+      pred.push_back(signalers[idx][target - 1]);
+    }
+    pred_off[t + 1] = (int32_t)pred.size();
+    int ns = task_nsignals(tk);
+    for (int q = 0; q < ns; ++q) {
+      int64_t idx = task_signal(tk, m, q);
+      if (idx < 0 || idx >= nctr) return -2;
+      signalers[idx].push_back((int32_t)t);
+    }
+  }
+  d.ndeps.assign(T, 0);
+  std::vector<int32_t> cnt(T + 1, 0);
+  for (int64_t t = 0; t < T; ++t) {
+    for (int32_t e = pred_off[t]; e < pred_off[t + 1]; ++e) cnt[pred[e] + 1]++;
+    d.ndeps[t] = pred_off[t + 1] - pred_off[t];
+  }
+  for (int64_t t = 0; t < T; ++t) cnt[t + 1] += cnt[t];
+  d.succ_off = cnt;
+  d.succ.assign(pred.size(), 0);
+  std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+  for (int64_t t = 0; t < T; ++t)
+    for (int32_t e = pred_off[t]; e < pred_off[t + 1]; ++e) d.succ[fill[pred[e]]++] = (int32_t)t;
+  return 0;
+}
+
+}  // namespace
+
+int build_order(const std::vector<MatDesc> &mats, bool apply, int workers,
+                std::vector<Task> &order, int64_t *counter_total) {
+  Dag d;
+  int rc = derive_dag(mats, apply, d);
+  if (rc != 0) return rc;
+  const int64_t T = (int64_t)d.tasks.size();
+  if (counter_total) {
+    int64_t nctr = 0;
+    for (const MatDesc &m : mats) {
+      int64_t e = m.ctr + (apply ? ctr_count_apply(m) : ctr_count_factor(m));
+      nctr = e > nctr ? e : nctr;
+    }
+    *counter_total = nctr;
+  }
+  std::vector<double> cost(T), bl(T);
+  for (int64_t t = 0; t < T; ++t) cost[t] = task_cost(d.tasks[t], mats[task_mat(d.tasks[t])]);
+  for (int64_t t = T - 1; t >= 0; --t) {
+    double b = 0.0;
+    for (int32_t e = d.succ_off[t]; e < d.succ_off[t + 1]; ++e) b = std::max(b, bl[d.succ[e]]);
+    bl[t] = cost[t] + b;
+  }
+  typedef std::pair<double, int32_t> RP;  // (bottom level, -index)
+  std::priority_queue<RP> ready;
+  typedef std::pair<double, int32_t> EV;  // (-finish, task)
+  std::priority_queue<EV> events;
+  std::vector<int32_t> rem(d.ndeps);
+  for (int64_t t = 0; t < T; ++t)
+    if (rem[t] == 0) ready.push(RP(bl[t], (int32_t)-t));
+  order.clear();
+  order.reserve(T);
+  double now = 0.0;
+  int free_w = workers > 0 ? workers : 1;
+  while ((int64_t)order.size() < T) {
+    while (free_w > 0 && !ready.empty()) {
+      int32_t t = -ready.top().second;
+      ready.pop();
+      order.push_back(d.tasks[t]);
+      events.push(EV(-(now + cost[t]), t));
+      --free_w;
+    }
+    if (events.empty()) return -4;  // cycle: cannot happen for a DAG
+    now = -events.top().first;
+    while (!events.empty() && -events.top().first <= now) {
+      int32_t t = events.top().second;
+      events.pop();
+      ++free_w;
+      for (int32_t e = d.succ_off[t]; e < d.succ_off[t + 1]; ++e) {
+        int32_t s = d.succ[e];
+        if (--rem[s] == 0) ready.push(RP(bl[s], -s));
+      }
+    }
+  }
+  return 0;
+}
+
+int64_t check_order_sequential(const std::vector<MatDesc> &mats, const std::vector<Task> &order) {
+  int64_t nctr = 0;
+  for (const MatDesc &m : mats) {
+    int64_t e = m.ctr + std::max(ctr_count_apply(m), ctr_count_factor(m));
+    nctr = e > nctr ? e : nctr;
+  }
+  std::vector<int32_t> ctr((size_t)nctr, 0);
+  int64_t bad = 0;
+  for (const Task &t : order) {
+    const MatDesc &m = mats[task_mat(t)];
+    int nw = task_nwaits(t, m);
+    for (int q = 0; q < nw; ++q) {
+      int64_t idx;
+      int target;
+      task_wait(t, m, q, &idx, &target);
+      if (ctr[idx] < target) ++bad;
+    }
+    int ns = task_nsignals(t);
+    for (int q = 0; q < ns; ++q) ctr[task_signal(t, m, q)]++;
+  }
+  return bad;
+}
+
+namespace {
+
+// Data items a task touches, written from what each kernel reads and writes
+// (independently of the counter protocol). The diagonal tile is split into
+// its R part (upper, rewritten by every TSQRT of the step) and its V part
+// (lower, read by the LARFBs of the step).
+struct Access {
+  int64_t item;
+  bool write;
+};
+
+int64_t item_strip(const MatDesc &m, int mat, int i, int j, int s) {
+  return ((int64_t)mat << 40) | ((((int64_t)i * m.NT + j) * m.S + s) * 4 + 0);
+}
+int64_t item_rpart(const MatDesc &m, int mat, int k) {
+  return ((int64_t)mat << 40) | ((((int64_t)k * m.NT + k) * m.S) * 4 + 1);
+}
+int64_t item_vpart(const MatDesc &m, int mat, int k) {
+  return ((int64_t)mat << 40) | ((((int64_t)k * m.NT + k) * m.S) * 4 + 2);
+}
+int64_t item_T(const MatDesc &m, int mat, int i, int k) {
+  return ((int64_t)mat << 40) | ((((int64_t)i * m.NT + k) * m.S) * 4 + 3);
+}
+int64_t item_B(const MatDesc &m, int mat, int i, int s) {
+  return ((int64_t)mat << 40) | ((int64_t)1 << 39) | ((int64_t)i * m.SB + s);
+}
+
+void accesses(const Task &t, const MatDesc &m, std::vector<Access> &a) {
+  a.clear();
+  int mat = task_mat(t), i = t.i, j = t.j, k = t.k, s = task_strip(t);
+  switch (task_type(t)) {
+    case TK_GEQRT:
+      for (int q = 0; q < strips_of(m, k); ++q) a.push_back({item_strip(m, mat, k, k, q), true});
+      a.push_back({item_rpart(m, mat, k), true});
+      a.push_back({item_vpart(m, mat, k), true});
+      a.push_back({item_T(m, mat, k, k), true});
+      break;
+    case TK_TSQRT:
+      a.push_back({item_rpart(m, mat, k), true});
+      for (int q = 0; q < strips_of(m, k); ++q) a.push_back({item_strip(m, mat, i, k, q), true});
+      a.push_back({item_T(m, mat, i, k), true});
+      break;
+    case TK_LARFB:
+      a.push_back({item_vpart(m, mat, k), false});
+      a.push_back({item_T(m, mat, k, k), false});
+      a.push_back({item_strip(m, mat, k, j, s), true});
+      break;
+    case TK_SSRFB:
+      for (int q = 0; q < strips_of(m, k); ++q) a.push_back({item_strip(m, mat, i, k, q), false});
+      a.push_back({item_T(m, mat, i, k), false});
+      a.push_back({item_strip(m, mat, k, j, s), true});
+      a.push_back({item_strip(m, mat, i, j, s), true});
+      break;
+    case TK_LARFB_B:
+      a.push_back({item_B(m, mat, k, s), true});
+      break;
+    case TK_SSRFB_B:
+      a.push_back({item_B(m, mat, k, s), true});
+      a.push_back({item_B(m, mat, i, s), true});
+      break;
+  }
+}
+
+}  // namespace
+
+int64_t stress_order(const std::vector<MatDesc> &mats, bool apply,
+                     const std::vector<Task> &order, int workers, uint64_t seed) {
+  // Program order and task identity.
+  std::vector<Task> prog;
+  for (size_t m = 0; m < mats.size(); ++m) {
+    if (apply) enum_apply_tasks(mats[m], (int)m, prog);
+    else enum_factor_tasks(mats[m], (int)m, prog);
+  }
+  const int64_t T = (int64_t)prog.size();
+  if ((int64_t)order.size() != T) return -2;
+  auto key = [](const Task &t) {
+    return ((uint64_t)(uint32_t)t.w0 << 32) ^ ((uint64_t)(uint32_t)t.i << 42) ^
+           ((uint64_t)(uint32_t)t.j << 21) ^ (uint64_t)(uint32_t)t.k;
+  };
+  std::unordered_map<uint64_t, int64_t> pos;
+  pos.reserve((size_t)T * 2);
+  for (int64_t p = 0; p < T; ++p) pos[key(prog[p])] = p;
+  int64_t nctr = 0;
+  for (const MatDesc &m : mats) {
+    int64_t e = m.ctr + (apply ? ctr_count_apply(m) : ctr_count_factor(m));
+    nctr = e > nctr ? e : nctr;
+  }
+  std::vector<int32_t> ctr((size_t)nctr, 0);
+  std::vector<double> start(T, -1.0), finish(T, -1.0);
+  std::mt19937_64 rng(seed);
+  std::uniform_real_distribution<double> dur(0.1, 10.0);
+
+  enum { IDLE, WAITING, RUNNING };
+  std::vector<int> state(workers, IDLE);
+  std::vector<int64_t> cur(workers, -1);
+  std::vector<double> end_t(workers, 0.0);
+  int64_t next = 0, done = 0;
+  double now = 0.0;
+  while (done < T) {
+    for (int w = 0; w < workers; ++w)
+      if (state[w] == IDLE && next < T) {
+        cur[w] = next++;
+        state[w] = WAITING;
+      }
+    for (int w = 0; w < workers; ++w) {
+      if (state[w] != WAITING) continue;
+      const Task &t = order[cur[w]];
+      const MatDesc &m = mats[task_mat(t)];
+      bool ok = true;
+      int nw = task_nwaits(t, m);
+      for (int q = 0; q < nw && ok; ++q) {
+        int64_t idx;
+        int target;
+        task_wait(t, m, q, &idx, &target);
+        ok = ctr[idx] >= target;
+      }
+      if (ok) {
+        state[w] = RUNNING;
+        end_t[w] = now + dur(rng);
+        start[pos[key(t)]] = now;
+      }
+    }
+    double tmin = 1e300;
+    for (int w = 0; w < workers; ++w)
+      if (state[w] == RUNNING && end_t[w] < tmin) tmin = end_t[w];
+    if (tmin == 1e300) return -1;  // everyone waits: deadlock
+    now = tmin;
+    for (int w = 0; w < workers; ++w) {
+      if (state[w] == RUNNING && end_t[w] <= now) {
+        const Task &t = order[cur[w]];
+        const MatDesc &m = mats[task_mat(t)];
+        int ns = task_nsignals(t);
+        for (int q = 0; q < ns; ++q) ctr[task_signal(t, m, q)]++;
+        finish[pos[key(t)]] = now;
+        state[w] = IDLE;
+        ++done;
+      }
+    }
+  }
+  // Hazard check in program order per data item.
+  struct Last {
+    int64_t last_write = -1;
+    std::vector<int64_t> reads_since;
+  };
+  std::unordered_map<int64_t, Last> items;
+  std::vector<Access> acc;
+  int64_t bad = 0;
+  for (int64_t p = 0; p < T; ++p) {
+    const Task &t = prog[p];
+    accesses(t, mats[task_mat(t)], acc);
+    for (const Access &a : acc) {
+      Last &L = items[a.item];
+      if (L.last_write >= 0 && finish[L.last_write] > start[p]) ++bad;
+      if (a.write) {
+        for (int64_t r : L.reads_since)
+          if (finish[r] > start[p]) ++bad;
+        L.reads_since.clear();
+        L.last_write = p;
+      } else {
+        L.reads_since.push_back(p);
+      }
+    }
+  }
+  return bad;
+}
