@@ -112,6 +112,13 @@ int qr_factor_loop(double *const *A, const int64_t *M, const int64_t *N, const i
  * error; 0 if none. */
 int qr_sync(void *stream);
 
+/* Task trace of the last qr_factor launched with TILEQR_TRACE=1 in the
+ * environment (development aid: shows where the DAG waits). Writes 9 int64
+ * per task in ticket order (host, capacity cap tasks): type, i, j, k, strip,
+ * ns when the task was taken, ns when its dependencies were met, ns when it
+ * finished, workgroup id. *ntasks receives the count. Synchronizes. */
+int qr_trace_fetch(int64_t *out, int64_t cap, int64_t *ntasks);
+
 /* ---------------------------------------------------------------------- */
 /* Single tile kernels (Section 2.1; used by the per-kernel checks)          */
 /* ---------------------------------------------------------------------- */

@@ -121,6 +121,19 @@ def sync(stream=None):
     check(_lib.lib().qr_sync(_stream(stream)), "qr_sync")
 
 
+def trace_fetch():
+    """Per-task trace of the last factorization run with TILEQR_TRACE=1:
+    an (ntasks, 9) int64 array (type, i, j, k, strip, t_take, t_ready,
+    t_done in ns, workgroup)."""
+    import numpy as np
+    n = ctypes.c_int64()
+    check(_lib.lib().qr_trace_fetch(None, 0, ctypes.byref(n)), "qr_trace_fetch")
+    out = np.zeros((max(1, n.value), 9), dtype=np.int64)
+    check(_lib.lib().qr_trace_fetch(out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n.value,
+                                    ctypes.byref(n)), "qr_trace_fetch")
+    return out[:n.value]
+
+
 def tile_task(kind, A, nb, ib, T, i, j, k, stream=None):
     M, N = A.shape
     check(_lib.lib().qr_tile_task(kind, ctypes.c_void_p(A.data_ptr()), M, N, _ld(A), nb, ib,

@@ -24,6 +24,7 @@ struct TqLaunch {
   size_t lds_bytes;
   int grid;
   int mbt;
+  long long *trace;     // optional: 4 wall-clock stamps per task, or nullptr
 };
 
 hipError_t tq_launch_persistent(const TqLaunch &a, hipStream_t st);

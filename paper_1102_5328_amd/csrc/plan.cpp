@@ -19,7 +19,7 @@ void md_init(MatDesc &md, int64_t M, int64_t N, int nb, int ib, int w, int64_t n
   md.S = (nb + w - 1) / w;
   md.nrhs = (int32_t)nrhs;
   md.SB = nrhs > 0 ? (int32_t)((nrhs + w - 1) / w) : 0;
-  md.pad = 0;
+  md.gmax = 1;
 }
 
 void enum_factor_tasks(const MatDesc &md, int mat, std::vector<Task> &out) {

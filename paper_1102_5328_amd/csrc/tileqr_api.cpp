@@ -117,10 +117,11 @@ void touch(const PlanKey &k) {
   }
 }
 
-int nw_for_mbt(int mbt, int ib) {
-  for (int nw = 4; nw >= 1; nw >>= 1)
-    if (lds_doubles(mbt, ib, nw) * 8 <= TQ_LDS_LIMIT) return nw;
-  return 0;
+// Geometry of one matrix for a kernel class: strip width and staged chunks.
+void md_setup(MatDesc &md, int64_t M, int64_t N, int nb, int ib, int mbt, int64_t nrhs) {
+  const LdsPlan lp = lds_plan(mbt, ib);
+  md_init(md, M, N, nb, ib, 16 * lp.nw, nrhs);
+  md.gmax = lp.gmax;
 }
 
 // Builds (or fetches) the plan of a set of matrices sharing one kernel class.
@@ -139,7 +140,7 @@ int get_plan(const PlanKey &key, std::vector<MatDesc> mats, bool apply, const De
   for (MatDesc &m : mats) {
     m.ctr = ctr;
     ctr += apply ? ctr_count_apply(m) : ctr_count_factor(m);
-    lds = std::max(lds, (size_t)lds_doubles(mbt, m.ib, m.w >> 4) * 8);
+    lds = std::max(lds, (size_t)lds_plan(mbt, m.ib).doubles * 8);
   }
   int occ = tq_occupancy(mbt, lds);
   int grid = std::max(1, ds.ncu * occ);
@@ -221,7 +222,37 @@ TqLaunch make_launch(const Plan &p, const DevState &ds, const MatDesc &single) {
   a.lds_bytes = p.lds;
   a.grid = p.grid;
   a.mbt = p.mbt;
+  a.trace = nullptr;
   return a;
+}
+
+// Optional per-task trace of the last traced launch (TILEQR_TRACE=1).
+struct TraceState {
+  long long *d = nullptr;
+  int64_t cap = 0, n = 0;
+  std::vector<Task> order;
+  int dev = -1;
+};
+TraceState g_trace;
+
+bool trace_on() {
+  const char *e = std::getenv("TILEQR_TRACE");
+  return e && e[0] == '1';
+}
+
+long long *trace_buffer(int64_t ntasks) {
+  int dev = 0;
+  hipGetDevice(&dev);
+  if (ntasks > g_trace.cap || dev != g_trace.dev) {
+    if (g_trace.d) hipFree(g_trace.d);
+    g_trace.d = nullptr;
+    g_trace.cap = 0;
+    if (hipMalloc(&g_trace.d, sizeof(long long) * 4 * ntasks) != hipSuccess) return nullptr;
+    g_trace.cap = ntasks;
+    g_trace.dev = dev;
+  }
+  g_trace.n = ntasks;
+  return g_trace.d;
 }
 
 bool nb_ok(int nb) { return nb >= 16 && nb <= 512; }
@@ -243,8 +274,7 @@ int factor_one(double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, dou
   if (M == 0 || N == 0) return 0;
   MatDesc md;
   std::memset(&md, 0, sizeof(md));
-  int nw = nw_for_mbt(mbt_for_nb(NB), IB);
-  md_init(md, M, N, NB, IB, 16 * nw, 0);
+  md_setup(md, M, N, NB, IB, mbt_for_nb(NB), 0);
   md.lda = lda;
   PlanKey key{0, 0, NB, IB, M, N, 0, 0};
   hipGetDevice(&key.dev);
@@ -256,6 +286,12 @@ int factor_one(double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, dou
   md.B = nullptr;
   md.ctr = 0;
   TqLaunch a = make_launch(*p, ds, md);
+  if (trace_on()) {
+    a.trace = trace_buffer(p->ntasks);
+    g_trace.order.resize(p->ntasks);
+    if (p->ntasks)
+      hipMemcpy(g_trace.order.data(), p->d_tasks, sizeof(Task) * p->ntasks, hipMemcpyDeviceToHost);
+  }
   if (tq_launch_persistent(a, st) != hipSuccess) return TILEQR_ERR_HIP;
   return 0;
 }
@@ -350,8 +386,7 @@ int qr_apply_Qt(const double *A, int64_t M, int64_t N, int64_t lda, int NB, int 
   if ((rc = dev_state(&ds))) return rc;
   MatDesc md;
   std::memset(&md, 0, sizeof(md));
-  int nw = nw_for_mbt(mbt_for_nb(NB), IB);
-  md_init(md, M, N, NB, IB, 16 * nw, nrhs);
+  md_setup(md, M, N, NB, IB, mbt_for_nb(NB), nrhs);
   if ((int64_t)md.SB > 4095) return TILEQR_ERR_TOO_LARGE;
   md.lda = lda;
   md.ldb = ldb;
@@ -422,8 +457,7 @@ int qr_factor_batched(double *const *A, const int64_t *M, const int64_t *N, cons
     if (M[b] == 0 || N[b] == 0) continue;
     MatDesc md;
     std::memset(&md, 0, sizeof(md));
-    int nw = nw_for_mbt(mbt, ibs[b]);
-    md_init(md, M[b], N[b], nbs[b], ibs[b], 16 * nw, 0);
+    md_setup(md, M[b], N[b], nbs[b], ibs[b], mbt, 0);
     md.lda = lda[b];
     md.A = A[b];
     md.T = T[b];
@@ -509,8 +543,7 @@ int qr_tile_task(int kind, double *A, int64_t M, int64_t N, int64_t lda, int NB,
   if (!nb_enabled(NB)) return TILEQR_ERR_DISABLED;
   MatDesc md;
   std::memset(&md, 0, sizeof(md));
-  int nw = nw_for_mbt(mbt_for_nb(NB), IB);
-  md_init(md, M, N, NB, IB, 16 * nw, 0);
+  md_setup(md, M, N, NB, IB, mbt_for_nb(NB), 0);
   md.lda = lda;
   md.A = A;
   md.T = T;
@@ -552,7 +585,7 @@ int qr_tile_task(int kind, double *A, int64_t M, int64_t N, int64_t lda, int NB,
                      st) != hipSuccess)
     rc = TILEQR_ERR_HIP;
   int mbt = mbt_for_nb(NB);
-  size_t lds = (size_t)lds_doubles(mbt, IB, nw) * 8;
+  size_t lds = (size_t)lds_plan(mbt, IB).doubles * 8;
   TqLaunch a;
   a.tasks = d_tasks;
   a.ntasks = (int64_t)tasks.size();
@@ -568,6 +601,7 @@ int qr_tile_task(int kind, double *A, int64_t M, int64_t N, int64_t lda, int NB,
   a.lds_bytes = lds;
   a.grid = (int)tasks.size();
   a.mbt = mbt;
+  a.trace = nullptr;
   if (!rc && tq_launch_persistent(a, st) != hipSuccess) rc = TILEQR_ERR_HIP;
   if (hipStreamSynchronize(st) != hipSuccess) rc = TILEQR_ERR_HIP;
   hipFree(d_tasks);
@@ -742,6 +776,35 @@ int qr_tune(int64_t M, int64_t N, int64_t batch, int *NB, int *IB, int *source) 
   return 0;
 }
 
+int qr_trace_fetch(int64_t *out, int64_t cap, int64_t *ntasks) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (ntasks) *ntasks = g_trace.n;
+  if (!out || !g_trace.d || g_trace.n == 0) return 0;
+  if (hipDeviceSynchronize() != hipSuccess) return TILEQR_ERR_HIP;
+  std::vector<long long> h((size_t)4 * g_trace.n);
+  if (hipMemcpy(h.data(), g_trace.d, sizeof(long long) * h.size(), hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return TILEQR_ERR_HIP;
+  DevState *ds;
+  int rc = dev_state(&ds);
+  if (rc) return rc;
+  for (int64_t t = 0; t < g_trace.n && t < cap; ++t) {
+    const Task &tk = g_trace.order[t];
+    int64_t *o = out + 9 * t;
+    o[0] = task_type(tk);
+    o[1] = tk.i;
+    o[2] = tk.j;
+    o[3] = tk.k;
+    o[4] = task_strip(tk);
+    // wall-clock ticks -> nanoseconds
+    o[5] = (int64_t)(h[4 * t + 0] * (1e6 / (double)ds->wall_khz));
+    o[6] = (int64_t)(h[4 * t + 1] * (1e6 / (double)ds->wall_khz));
+    o[7] = (int64_t)(h[4 * t + 2] * (1e6 / (double)ds->wall_khz));
+    o[8] = h[4 * t + 3];
+  }
+  return 0;
+}
+
 // --------------------------------------------------------- host inspection
 
 int qr_dag_counts(int64_t M, int64_t N, int NB, int64_t *counts) {
@@ -799,7 +862,7 @@ int qr_plan_check(int64_t M, int64_t N, int NB, int IB, int64_t nrhs, int apply,
   if (M < 1 || N < 1 || !nb_ok(NB) || IB < 1 || IB > NB || workers < 1) return TILEQR_ERR_INTERNAL;
   MatDesc md;
   std::memset(&md, 0, sizeof(md));
-  md_init(md, M, N, NB, IB, 16 * nw_for_mbt(mbt_for_nb(NB), IB), apply ? nrhs : 0);
+  md_setup(md, M, N, NB, IB, mbt_for_nb(NB), apply ? nrhs : 0);
   md.ctr = 0;
   std::vector<MatDesc> mats{md};
   std::vector<Task> order;
@@ -816,7 +879,7 @@ int qr_plan_tasks(int64_t M, int64_t N, int NB, int IB, int64_t nrhs, int apply,
   if (M < 1 || N < 1 || !nb_ok(NB) || IB < 1 || IB > NB || workers < 1) return TILEQR_ERR_INTERNAL;
   MatDesc md;
   std::memset(&md, 0, sizeof(md));
-  md_init(md, M, N, NB, IB, 16 * nw_for_mbt(mbt_for_nb(NB), IB), apply ? nrhs : 0);
+  md_setup(md, M, N, NB, IB, mbt_for_nb(NB), apply ? nrhs : 0);
   md.ctr = 0;
   std::vector<MatDesc> mats{md};
   std::vector<Task> order;

@@ -68,7 +68,7 @@ struct MatDesc {
   int32_t w;     // strip width in columns (16 * active waves)
   int32_t nrhs;  // columns of B
   int32_t SB;    // strips of B (ceil(nrhs / w))
-  int32_t pad;
+  int32_t gmax;  // V chunks staged in LDS at once
 };
 
 TQ_HD inline int tile_rows(const MatDesc &m, int i) {

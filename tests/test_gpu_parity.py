@@ -60,7 +60,9 @@ def test_leading_dimension_padding():
     _assert_ok(r)
 
 
-@pytest.mark.parametrize("M,N,nb,ib", [(64, 64, 64, 16), (100, 60, 128, 32), (50, 90, 64, 24),
+@pytest.mark.parametrize("M,N,nb,ib", [(128, 16, 128, 16), (128, 8, 128, 8), (100, 16, 128, 16),
+                                       (64, 16, 64, 16), (70, 12, 128, 12),
+                                       (64, 64, 64, 16), (100, 60, 128, 32), (50, 90, 64, 24),
                                        (128, 128, 128, 128),
                                        pytest.param(256, 200, 256, 48,
                                                     marks=pytest.mark.skip(reason=NB_OFF))])
