@@ -1,0 +1,231 @@
+"""The C ABI on the host (no device needed): every entry point declared in
+include/tileqr.h is exported by libtileqr.so; argument checking follows the
+LAPACK info convention; the tile DAG (Section 2.1) has the task counts the
+tiling fixes and its host-built order is a valid schedule; the flop model
+shows the inner-blocking overhead of Section 2.2; qr_tune interpolates the
+decision table as Section 6.1 describes.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1102_5328_amd as tq
+from paper_1102_5328_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tileqr.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1102_5328_amd import build
+        build.build()
+    return _lib.lib()
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(qr_[A-Za-z0-9_]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 20
+    raw = ctypes.CDLL(_lib.LIB_PATH)
+    missing = [n for n in names if not hasattr(raw, n)]
+    assert not missing
+    # ... and the binding describes each of them.
+    assert sorted(_lib.SIGNATURES) == names
+
+
+def test_version(lib):
+    assert lib.qr_version().decode().startswith("tileqr")
+
+
+# ------------------------------------------------------ argument checking
+
+
+def test_factor_argument_errors(lib):
+    f = lib.qr_factor
+    p = ctypes.c_void_p(16)  # never dereferenced: every call below fails its checks first
+    assert f(p, -1, 4, 4, 64, 16, p, None) == -2
+    assert f(p, 4, -1, 4, 64, 16, p, None) == -3
+    assert f(None, 4, 4, 4, 64, 16, p, None) == -1
+    assert f(p, 8, 4, 7, 64, 16, p, None) == -4
+    assert f(p, 8, 4, 8, 8, 4, p, None) == -5
+    assert f(p, 8, 4, 8, 1024, 16, p, None) == -5
+    assert f(p, 8, 4, 8, 64, 65, p, None) == -6
+    assert f(p, 8, 4, 8, 64, -1, p, None) == -6
+    assert f(p, 8, 4, 8, 64, 16, None, None) == -7
+    assert f(p, 8, 4, 8, 256, 32, p, None) == 8  # TILEQR_ERR_DISABLED
+
+
+def test_apply_argument_errors(lib):
+    f = lib.qr_apply_Qt
+    p = ctypes.c_void_p(16)
+    assert f(None, 8, 4, 8, 64, 16, p, p, 2, 8, None) == -1
+    assert f(p, -8, 4, 8, 64, 16, p, p, 2, 8, None) == -2
+    assert f(p, 8, -4, 8, 64, 16, p, p, 2, 8, None) == -3
+    assert f(p, 8, 4, 2, 64, 16, p, p, 2, 8, None) == -4
+    assert f(p, 8, 4, 8, 8, 4, p, p, 2, 8, None) == -5
+    assert f(p, 8, 4, 8, 64, 65, p, p, 2, 8, None) == -6
+    assert f(p, 8, 4, 8, 64, 16, None, p, 2, 8, None) == -7
+    assert f(p, 8, 4, 8, 64, 16, p, None, 2, 8, None) == -8
+    assert f(p, 8, 4, 8, 64, 16, p, p, -2, 8, None) == -9
+    assert f(p, 8, 4, 8, 64, 16, p, p, 2, 4, None) == -10
+
+
+def test_other_argument_errors(lib):
+    sec = ctypes.c_double()
+    assert lib.qr_ssrfb_bench(8, 4, 1, 0, ctypes.byref(sec)) == -1
+    assert lib.qr_ssrfb_bench(64, 65, 1, 0, ctypes.byref(sec)) == -2
+    assert lib.qr_ssrfb_bench(64, 16, 0, 0, ctypes.byref(sec)) == -3
+    assert lib.qr_ssrfb_bench(64, 16, 1, -1, ctypes.byref(sec)) == -4
+    assert lib.qr_ssrfb_bench(64, 16, 1, 0, None) == -5
+    assert lib.qr_T_size(-1, 4, 64, 16) == -1
+    assert lib.qr_T_size(4, -1, 64, 16) == -2
+    assert lib.qr_T_size(4, 4, 0, 16) == -3
+    assert lib.qr_T_size(4, 4, 64, 0) == -4
+    nb, ib, src = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    assert lib.qr_tune(-1, 4, 1, ctypes.byref(nb), ctypes.byref(ib), None) == -1
+    assert lib.qr_tune(4, -1, 1, ctypes.byref(nb), ctypes.byref(ib), None) == -2
+    assert lib.qr_tune(4, 4, 0, ctypes.byref(nb), ctypes.byref(ib), None) == -3
+    assert lib.qr_tune(4, 4, 1, None, ctypes.byref(ib), None) == -4
+    assert lib.qr_tune(4, 4, 1, ctypes.byref(nb), None, None) == -5
+    assert lib.qr_tune_load(None) == -1
+    assert lib.qr_tune_load(b"/nonexistent/table.txt") == 7
+
+
+def test_T_size(lib):
+    # KT * MT * IB * NB
+    assert tq.T_size(512, 512, 128, 32) == 4 * 4 * 32 * 128
+    assert tq.T_size(1000, 300, 96, 24) == 4 * 11 * 24 * 96
+    assert tq.T_size(300, 1000, 96, 24) == 4 * 4 * 24 * 96
+    assert tq.T_size(0, 10, 64, 16) == 0
+
+
+# ---------------------------------------------------------------- tile DAG
+
+
+@pytest.mark.parametrize("M,N,nb,counts", [
+    (512, 512, 128, [4, 6, 6, 14]),
+    (16384, 16384, 256, [64, 2016, 2016, 85344]),
+    (16384, 16384, 64, [256, 32640, 32640, 5559680]),
+    (65536, 256, 64, [4, 4086, 6, 6134]),
+    (100, 300, 64, [2, 1, 7, 4]),
+])
+def test_dag_counts(lib, M, N, nb, counts):
+    """GEQRT / TSQRT / LARFB / SSRFB counts: KT, sum_k (MT-k-1), sum_k (NT-k-1),
+    sum_k (MT-k-1)(NT-k-1)."""
+    assert tq.dag_counts(M, N, nb) == counts
+    MT, NT = -(-M // nb), -(-N // nb)
+    KT = min(MT, NT)
+    assert counts == [KT, sum(MT - k - 1 for k in range(KT)), sum(NT - k - 1 for k in range(KT)),
+                      sum((MT - k - 1) * (NT - k - 1) for k in range(KT))]
+
+
+@pytest.mark.parametrize("M,N,nb,ib,workers,apply,nrhs", [
+    (512, 512, 128, 32, 256, False, 0),
+    (1000, 700, 96, 24, 64, False, 0),
+    (700, 1000, 64, 16, 8, False, 0),
+    (4096, 256, 64, 32, 256, False, 0),
+    (777, 333, 64, 12, 32, True, 5),
+])
+def test_plan_is_a_valid_schedule(lib, M, N, nb, ib, workers, apply, nrhs):
+    """The ticket order replays sequentially with every wait satisfied (seq =
+    0 violations), and a randomized parallel replay with `workers` workers
+    shows no read/write hazard on any tile (stress = 0)."""
+    for seed in (0, 1):
+        nt, seq, stress = tq.plan_check(M, N, nb, ib, nrhs=nrhs, apply=apply, workers=workers,
+                                        seed=seed)
+        assert nt > 0 and seq == 0 and stress == 0
+
+
+def test_plan_task_multiset(lib):
+    """Each tile task appears once per column strip; the order starts with
+    GEQRT(0)."""
+    tasks = tq.plan_tasks(512, 512, 128, 32)
+    assert tuple(tasks[0][:4]) == (0, 0, 0, 0)
+    types = sorted(set(int(t) for t in tasks[:, 0]))
+    assert types == [0, 1, 2, 3]
+    geqrt = {(int(t[1]), int(t[3])) for t in tasks if t[0] == 0}
+    assert geqrt == {(k, k) for k in range(4)}
+    ss = {(int(t[1]), int(t[2]), int(t[3])) for t in tasks if t[0] == 3}
+    assert ss == {(i, j, k) for k in range(4) for i in range(k + 1, 4) for j in range(k + 1, 4)}
+
+
+# ------------------------------------------------------------- flop model
+
+
+def test_flops_formula(lib):
+    assert tq.flops(1000, 1000) == pytest.approx(4.0 / 3.0 * 1e9)
+    assert tq.flops(2000, 1000) == pytest.approx(2 * 2000 * 1e6 - 2e9 / 3)
+    assert tq.flops(1000, 2000) == pytest.approx(2 * 2000 * 1e6 - 2e9 / 3)
+
+
+def test_inner_blocking_overhead(lib):
+    """Executed flops / algorithmic flops tends to 1 + IB/(4 NB) + 1/(2 NB)
+    as the tile count grows: the T_s products add IB*NB^2 per DSSRFB on top
+    of its 4 NB^3 (Section 2.2: IB = NB costs 25 % more), and the additions
+    into the top tile 2 NB^2."""
+    for nb, ib in ((128, 32), (64, 64), (128, 128)):
+        lim = 1.0 + ib / (4.0 * nb) + 1.0 / (2.0 * nb)
+        errs = [abs(tq.flops_executed(n, n, nb, ib) / tq.flops(n, n) - lim)
+                for n in (4096, 16384, 65536)]
+        assert errs[0] > errs[1] > errs[2]
+        assert errs[2] < 5e-5
+
+
+# ------------------------------------------------------------- qr_tune
+
+
+def _table(tmp_path, entries, default=(128, 32)):
+    p = tmp_path / "table.txt"
+    with open(p, "w") as f:
+        f.write("# test table\ndefault %d %d\n" % default)
+        for e in entries:
+            f.write("entry %d %d %d %d %d %.1f\n" % e)
+    return str(p)
+
+
+def test_tune_interpolation_examples(lib, tmp_path, monkeypatch):
+    """Section 6.1: 2700 is answered by 2000 and 4200 by 4000 on a grid
+    {1000, 2000, 4000, 6000}; a point between batch 4 and 8 (the paper's
+    ncores axis) at 5 is answered by 4."""
+    monkeypatch.delenv("TILEQR_NB", raising=False)
+    monkeypatch.delenv("TILEQR_IB", raising=False)
+    ents = [(1000, 1000, 1, 64, 16, 1), (2000, 2000, 1, 96, 32, 2), (4000, 4000, 1, 128, 32, 3),
+            (6000, 6000, 1, 128, 64, 4), (2000, 2000, 4, 64, 32, 5), (2000, 2000, 8, 128, 16, 6)]
+    tq.tune_load(_table(tmp_path, ents))
+    try:
+        assert tq.tune(2700, 2700, 1) == (96, 32, 1)
+        assert tq.tune(4200, 4200, 1) == (128, 32, 1)
+        assert tq.tune(1800, 1800, 5) == (64, 32, 1)
+        assert tq.tune(10 ** 6, 10 ** 6, 1) == (128, 64, 1)
+        # Equidistant in log space from 1000 and 4000: the larger wins.
+        assert tq.tune(2000, 2000, 2)[:2] in ((96, 32), (64, 32))
+        ents2 = [(1000, 1000, 1, 64, 16, 1), (4000, 4000, 1, 128, 32, 3)]
+        tq.tune_load(_table(tmp_path, ents2))
+        assert tq.tune(2000, 2000, 1) == (128, 32, 1)
+        # Environment override.
+        monkeypatch.setenv("TILEQR_NB", "96")
+        monkeypatch.setenv("TILEQR_IB", "48")
+        assert tq.tune(2000, 2000, 1) == (96, 48, 3)
+    finally:
+        monkeypatch.delenv("TILEQR_NB", raising=False)
+        monkeypatch.delenv("TILEQR_IB", raising=False)
+        tq.tune_load(_table(tmp_path, []))
+    # An empty table: the default, source 0.
+    assert tq.tune(5000, 5000, 1) == (128, 32, 0)
+
+
+def test_tune_load_rejects_malformed(lib, tmp_path):
+    p = tmp_path / "bad.txt"
+    p.write_text("entry 100 100 1 8 4 1.0\n")  # NB below 16
+    assert lib.qr_tune_load(str(p).encode()) == 7
+    p.write_text("garbage\n")
+    assert lib.qr_tune_load(str(p).encode()) == 7
