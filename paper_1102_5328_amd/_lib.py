@@ -62,6 +62,9 @@ def lib():
             raise TileQRError(
                 "libtileqr.so not built: run `python -m paper_1102_5328_amd.build` "
                 "(or __graft_entry__.build())")
+        # torch ships its own HIP runtime; load it first so that the library
+        # binds to the same one (one runtime per process, one device context).
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(L, name)

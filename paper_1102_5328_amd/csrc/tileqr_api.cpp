@@ -100,7 +100,7 @@ struct PlanKey {
 
 std::map<PlanKey, Plan *> g_plans;
 std::list<PlanKey> g_lru;
-const size_t kMaxPlans = 64;
+const size_t kMaxPlans = 4096;
 
 void touch(const PlanKey &k) {
   g_lru.remove(k);

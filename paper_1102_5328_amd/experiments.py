@@ -1,0 +1,457 @@
+"""End-to-end measurement flows on one GPU, each writing a JSON report:
+
+  batched  2000 uneven matrices (M ~ U{64..1024}, N ~ U{32..M},
+           uniform[-1, 1], seed 0), tiles per size class from qr_tune:
+           one graph-captured persistent launch vs a loop of per-matrix
+           launches (time ratio; results compared bit for bit).
+  sweep    square N in {2048, 4096, 8192, 16384}, N(0, 1): GFLOP/s per
+           (N, NB, IB) over the enabled grid (median of 6 after a warm-up).
+  tune     the paper's pruned search (Step 1 -> heuristic -> Step 2 with and
+           without pruning as you go) vs exhaustive search on tall, wide,
+           square and ill-conditioned shapes; decision tables and tuning time.
+  mlp      the learned cost model: timings -> training set, an ensemble of
+           five 5-64-64-64-1 MLPs trained by the library's kernels, (NB, IB)
+           predicted for 200 held-out shapes (M, N log-uniform in
+           [256, 32768], seed 5), regret vs exhaustive search, fallback rate
+           and gain over the decision table alone.
+
+    python -m paper_1102_5328_amd.experiments {batched,sweep,tune} --out DIR [--db FILE]
+    python -m paper_1102_5328_amd.experiments {collect-train,collect-heldout} --db FILE
+                                              --out DIR [--budget SECONDS]
+    python -m paper_1102_5328_amd.experiments mlp --db FILE --out DIR
+    python -m paper_1102_5328_amd.experiments ship --out DIR   (DIR: a tune run's output)
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import inputs
+from .tuner import runner as R
+from .tuner import step2 as S2
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TUNING = os.path.join(HERE, "tuning")
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+# ------------------------------------------------------------------ batched
+
+
+def batched(out_dir, count=2000, seed=0, reps=5):
+    import torch
+    import paper_1102_5328_amd as tq
+    table = os.path.join(TUNING, "decision_table.txt")
+    if os.path.exists(table):
+        tq.tune_load(table)
+    shapes = inputs.batch_shapes(count, seed=seed)
+    mats = inputs.batch_matrices(shapes, seed=seed)
+    til = [tq.tune(m, n, count)[:2] for m, n in shapes]
+    nbs, ibs = [t[0] for t in til], [t[1] for t in til]
+    A0, As, Ts = [], [], []
+    for (m, n), a, nb, ib in zip(shapes, mats, nbs, ibs):
+        d = tq.colmajor(m, n)
+        d.copy_(torch.from_numpy(np.ascontiguousarray(a.T)).t())
+        A0.append(d)
+        As.append(tq.colmajor(m, n))
+        Ts.append(torch.empty(max(1, tq.T_size(m, n, nb, ib)), dtype=torch.float64, device="cuda"))
+    flops = sum(tq.flops(m, n) for m, n in shapes)
+
+    def restore():
+        for a, a0 in zip(As, A0):
+            a.copy_(a0)
+
+    def timed(fn):
+        ts = []
+        for _ in range(reps + 1):
+            restore()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn(As, nbs, ibs, Ts)
+            tq.sync()
+            ts.append(time.perf_counter() - t0)
+        return ts[1:]
+
+    t_loop = timed(tq.factor_loop)
+    ref = [a.clone() for a in As]
+    t_batch = timed(tq.factor_batched)
+    same = all(torch.equal(a, r) for a, r in zip(As, ref))
+    maxrel = max(float(torch.linalg.norm(a - r) / torch.linalg.norm(r)) for a, r in zip(As, ref))
+    classes = {}
+    for nb, ib in til:
+        classes["%d,%d" % (nb, ib)] = classes.get("%d,%d" % (nb, ib), 0) + 1
+    rep = {
+        "count": count, "seed": seed, "flops": flops,
+        "bytes": sum(8 * m * n for m, n in shapes),
+        "tilings": classes,
+        "loop_ms": [1e3 * t for t in t_loop], "batched_ms": [1e3 * t for t in t_batch],
+        "loop_ms_median": 1e3 * float(np.median(t_loop)),
+        "batched_ms_median": 1e3 * float(np.median(t_batch)),
+        "speedup": float(np.median(t_loop) / np.median(t_batch)),
+        "batched_gflops": flops / float(np.median(t_batch)) / 1e9,
+        "loop_gflops": flops / float(np.median(t_loop)) / 1e9,
+        "bitwise_equal": bool(same), "max_rel_diff_batched_vs_loop": maxrel,
+        "timing": "host wall clock around the call and qr_sync, inputs restored before each "
+                  "run (not timed); median of %d after one warm-up" % reps,
+    }
+    log("batched: loop %.2f ms, batched %.2f ms, speedup %.1fx, equal %s" %
+        (rep["loop_ms_median"], rep["batched_ms_median"], rep["speedup"], same))
+    with open(os.path.join(out_dir, "batched_report.json"), "w") as f:
+        json.dump(rep, f, indent=1)
+    return rep
+
+
+def _pow2_class(x):
+    c = 1
+    while c < x:
+        c *= 2
+    return c
+
+
+def batched_tune(out_dir, db, count=2000, seed=0, reps=3):
+    """Step 2 for the batch: the matrices are grouped in size classes
+    (M and N rounded up to powers of two); for each class, every enabled
+    (NB, IB) is timed on a batched launch of the class's matrices and the
+    fastest is recorded as a decision-table entry for (class M, class N,
+    batch count). Returns the entries."""
+    import torch
+    import paper_1102_5328_amd as tq
+    shapes = inputs.batch_shapes(count, seed=seed)
+    mats = inputs.batch_matrices(shapes, seed=seed)
+    classes = {}
+    for b, (m, n) in enumerate(shapes):
+        classes.setdefault((_pow2_class(m), _pow2_class(n)), []).append(b)
+    meas = R.Measurer(db)
+    pairs = R.config2_pairs()
+    entries = {}
+    t0 = time.perf_counter()
+    for (cm, cn), idx in sorted(classes.items()):
+        A0 = []
+        for b in idx:
+            d = tq.colmajor(*shapes[b])
+            d.copy_(torch.from_numpy(np.ascontiguousarray(mats[b].T)).t())
+            A0.append(d)
+        As = [tq.colmajor(*shapes[b]) for b in idx]
+        fl = sum(tq.flops(*shapes[b]) for b in idx)
+        res = {}
+        for nb, ib in pairs:
+            key = "batched:%d:%d:%d:%d:%d" % (cm, cn, nb, ib, count)
+            if key not in meas.db:
+                Ts = [torch.empty(max(1, tq.T_size(*shapes[b], nb, ib)), dtype=torch.float64,
+                                  device="cuda") for b in idx]
+                nbs, ibs = [nb] * len(idx), [ib] * len(idx)
+                ts = []
+                for r in range(reps + 1):
+                    for a, a0 in zip(As, A0):
+                        a.copy_(a0)
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    tq.factor_batched(As, nbs, ibs, Ts)
+                    tq.sync()
+                    ts.append(time.perf_counter() - t1)
+                g = [fl / t / 1e9 for t in ts[1:]]
+                gm = float(np.median(g))
+                # M, N of the record: the class's geometric-mean shape.
+                mg = int(round(math.exp(np.mean([math.log(shapes[b][0]) for b in idx]))))
+                ng = int(round(math.exp(np.mean([math.log(shapes[b][1]) for b in idx]))))
+                meas.db[key] = {"gflops": gm, "max": max(g), "runs": g, "seconds": sum(ts),
+                                "M": mg, "N": ng, "nb": nb, "ib": ib, "batch": count,
+                                "kind": "batched", "class": [cm, cn], "matrices": len(idx)}
+            res[(nb, ib)] = meas.db[key]["gflops"]
+        best = max(res, key=lambda p: (res[p], -p[0]))
+        rec = meas.db["batched:%d:%d:%d:%d:%d" % (cm, cn, best[0], best[1], count)]
+        entries[(rec["M"], rec["N"])] = (best[0], best[1], res[best])
+        log("batch class %dx%d (%d matrices): best %s %.1f GFLOP/s (%.0f s)" %
+            (cm, cn, len(idx), best, res[best], time.perf_counter() - t0))
+        meas.save()
+    with open(os.path.join(out_dir, "batched_tune.json"), "w") as f:
+        json.dump({"%dx%d" % k: list(v) for k, v in entries.items()}, f, indent=1)
+    return entries
+
+
+# ------------------------------------------------------------- sweep / tune
+
+
+def sweep(out_dir, db):
+    m = R.Measurer(db, reps=6)
+    s1, t1 = R.step1_gpu(R.config2_pairs())
+    log("step1 (%.1f s): %s" % (t1, {"%d,%d" % p: round(v, 1) for p, v in s1.items()}))
+    res = R.sweep_square(m, log=log)
+    m.save()
+    with open(os.path.join(out_dir, "sweep_report.json"), "w") as f:
+        json.dump({"step1_gflops": {"%d,%d" % p: v for p, v in s1.items()}, "step1_seconds": t1,
+                   "sweep": res}, f, indent=1)
+    return res
+
+
+def tune(out_dir, db):
+    m = R.Measurer(db, reps=6)
+    rep = R.tune_search(m, out_dir, log=log)
+    m.save()
+    return rep
+
+
+def ship_table(tune_dir, out_path, heuristic="2r", batch_count=2000):
+    """The decision table the library ships: the Step-2 (PSPAYG) decisions
+    of `heuristic` for single matrices plus the per-size-class decisions of
+    the batched tuning (entries with the batch count)."""
+    src = os.path.join(tune_dir, "decision_table_h%s_pspayg.txt" % heuristic)
+    entries = []
+    default = (128, 16)
+    with open(src) as f:
+        for line in f:
+            w = line.split()
+            if w and w[0] == "entry":
+                entries.append(tuple(int(x) for x in w[1:6]) + (float(w[6]),))
+    bt = os.path.join(tune_dir, "batched_tune.json")
+    if os.path.exists(bt):
+        with open(bt) as f:
+            for k, (nb, ib, g) in json.load(f).items():
+                m, n = (int(x) for x in k.split("x"))
+                entries.append((m, n, batch_count, nb, ib, g))
+    big = max((e for e in entries if e[2] == 1), key=lambda e: e[0] * e[1], default=None)
+    if big is not None:
+        default = (big[3], big[4])
+    with open(out_path, "w") as f:
+        f.write("# tileqr decision table: entry M N batch NB IB gflops\n")
+        f.write("# single matrices: Step 2 with pruning as you go over the pairs of heuristic %s;\n"
+                % heuristic)
+        f.write("# batch %d: per size class (M, N rounded up to powers of two; the entry holds\n"
+                "# the class's geometric-mean shape)\n" % batch_count)
+        f.write("default %d %d\n" % default)
+        for e in sorted(entries, key=lambda e: (e[2], e[0], e[1])):
+            f.write("entry %d %d %d %d %d %.3f\n" % e)
+    return entries
+
+
+# -------------------------------------------------------------------- MLP
+
+NP = 8769
+
+
+def features(M, N, nb, ib, batch):
+    return [math.log(M), math.log(N), math.log(nb), ib / float(nb), math.log(batch)]
+
+
+def _training_rows(db):
+    X, y = [], []
+    for r in db.values():
+        if r.get("kind", "normal") not in ("normal", "batched") or r["gflops"] <= 0:
+            continue
+        X.append(features(r["M"], r["N"], r["nb"], r["ib"], r.get("batch", 1)))
+        y.append(math.log(r["gflops"]))
+    return np.array(X, dtype=np.float64), np.array(y, dtype=np.float64)
+
+
+def _init_params(seed):
+    """He-uniform weights, zero biases."""
+    rng = np.random.default_rng(seed)
+    p = np.zeros(NP, dtype=np.float32)
+
+    def fill(off, fan_out, fan_in):
+        lim = math.sqrt(6.0 / fan_in)
+        p[off:off + fan_out * fan_in] = rng.uniform(-lim, lim, size=fan_out * fan_in)
+    fill(0, 64, 5)
+    fill(384, 64, 64)
+    fill(4544, 64, 64)
+    fill(8704, 1, 64)
+    return p
+
+
+def train_ensemble(X, y, nmodels=5, epochs=300, batch=64, lr=1e-3, seed=0):
+    """Standardises features and targets and trains `nmodels` models at once
+    with the library's kernels. Returns (params, fmean, fstd, ymean, ystd,
+    final losses, seconds)."""
+    import torch
+    import paper_1102_5328_amd as tq
+    from . import _lib
+    fmean, fstd = X.mean(0), X.std(0)
+    fstd[fstd == 0] = 1.0
+    ymean, ystd = float(y.mean()), float(y.std() or 1.0)
+    Xs = ((X - fmean) / fstd).astype(np.float32)
+    ys = ((y - ymean) / ystd).astype(np.float32)
+    p0 = np.stack([_init_params(seed + m) for m in range(nmodels)])
+    dp = torch.from_numpy(p0).cuda()
+    adam = torch.zeros(2 * nmodels * NP, dtype=torch.float32, device="cuda")
+    dX = torch.from_numpy(np.ascontiguousarray(Xs)).cuda()
+    dy = torch.from_numpy(ys).cuda()
+    lo = torch.empty(nmodels, dtype=torch.float32, device="cuda")
+    t0 = time.perf_counter()
+    step = 0
+    chunk = 25
+    steps_per_epoch = (len(ys) + batch - 1) // batch
+    for e0 in range(0, epochs, chunk):
+        ne = min(chunk, epochs - e0)
+        tq.check(_lib.lib().qr_mlp_train(dp.data_ptr(), nmodels, adam.data_ptr(), dX.data_ptr(),
+                                         dy.data_ptr(), len(ys), ne, batch, lr, seed, step,
+                                         lo.data_ptr(), None), "qr_mlp_train")
+        torch.cuda.synchronize()
+        step += ne * steps_per_epoch
+        log("  mlp epochs %d: loss %s" % (e0 + ne, np.round(lo.cpu().numpy(), 4).tolist()))
+    sec = time.perf_counter() - t0
+    return (dp.cpu().numpy(), fmean, fstd, ymean, ystd, lo.cpu().numpy().tolist(), sec)
+
+
+TRAIN_SHAPES = dict(count=420, seed=11, lo=256, hi=16384)
+TEST_SHAPES = dict(count=200, seed=5)
+
+
+def _shape_sets():
+    test_shapes = inputs.log_uniform_shapes(TEST_SHAPES["count"], seed=TEST_SHAPES["seed"])
+    tset = set(test_shapes)
+    train = inputs.log_uniform_shapes(TRAIN_SHAPES["count"], seed=TRAIN_SHAPES["seed"],
+                                      lo=TRAIN_SHAPES["lo"], hi=TRAIN_SHAPES["hi"])
+    return [s for s in train if s not in tset], test_shapes
+
+
+def collect(db, which, budget_s, reps=2):
+    """Measures every enabled (NB, IB) pair on the training shapes (kind
+    'normal') or on the held-out shapes (kind 'heldout': never used for
+    training) until done or `budget_s` seconds have passed; resumable, the
+    database keeps what was measured. Returns True when complete."""
+    pairs = R.config2_pairs()
+    meas = R.Measurer(db, reps=reps)
+    train, test = _shape_sets()
+    shapes, kind = (train, "normal") if which == "train" else (test, "heldout")
+    t0 = time.perf_counter()
+    done = True
+    for q, (M, N) in enumerate(shapes):
+        if time.perf_counter() - t0 > budget_s:
+            done = False
+            break
+        for nb, ib in pairs:
+            meas.measure(M, N, nb, ib, kind=kind)
+        if q % 5 == 0:
+            meas.save()
+        log("%s shape %d/%d %dx%d (%.0f s)" % (which, q + 1, len(shapes), M, N,
+                                                time.perf_counter() - t0))
+    meas.save()
+    return done
+
+
+def mlp(out_dir, db):
+    """Trains the ensemble on the database's timings and evaluates it on the
+    held-out shapes (which must all have been measured)."""
+    import paper_1102_5328_amd as tq
+    pairs = R.config2_pairs()
+    meas = R.Measurer(db)
+    _, test_shapes = _shape_sets()
+    es = {}
+    for (M, N) in test_shapes:
+        es[(M, N)] = {p: meas.db[R.Measurer.key("heldout", M, N, p[0], p[1])]["gflops"]
+                      for p in pairs}
+    X, y = _training_rows(meas.db)
+    log("training rows: %d" % len(y))
+    params, fmean, fstd, ymean, ystd, losses, t_train = train_ensemble(X, y)
+    cand = np.array(pairs, dtype=np.int32).reshape(-1)
+    table = os.path.join(TUNING, "decision_table.txt")
+    tq.tune_load(table if os.path.exists(table) else os.devnull)
+    ps = None
+    rep_path = os.path.join(TUNING, "tuning_report.json")
+    if os.path.exists(rep_path):
+        with open(rep_path) as f:
+            ps = [tuple(p) for p in json.load(f)["heuristics"]["2"]["PS"]]
+    ps = ps or pairs
+    rows = []
+    t_choose = 0.0
+    for (M, N) in test_shapes:
+        tq.check(_lib_set_model(None, 0, fmean, fstd, ymean, ystd, cand), "model off")
+        tnb, tib, _ = tq.tune(M, N, 1)
+        tq.check(_lib_set_model(params, len(params), fmean, fstd, ymean, ystd, cand), "model on")
+        t0 = time.perf_counter()
+        mnb, mib, src = tq.tune(M, N, 1)
+        t_choose += time.perf_counter() - t0
+        best = max(es[(M, N)], key=lambda p: es[(M, N)][p])
+        pbest = es[(M, N)][best]
+        fallback = bool(src & 8)
+        # Fallback: the pruned search on this shape, i.e. the best pre-selected pair.
+        choice = max(ps, key=lambda p: es[(M, N)][p]) if fallback else (mnb, mib)
+        rows.append({"M": M, "N": N, "best": list(best), "best_gflops": pbest,
+                     "model": [mnb, mib], "fallback": fallback, "chosen": list(choice),
+                     "chosen_gflops": es[(M, N)][choice], "table": [tnb, tib],
+                     "table_gflops": es[(M, N)].get((tnb, tib), float("nan"))})
+    _lib_set_model(None, 0, fmean, fstd, ymean, ystd, cand)
+    reg = np.array([1.0 - r["chosen_gflops"] / r["best_gflops"] for r in rows])
+    reg_t = np.array([1.0 - r["table_gflops"] / r["best_gflops"] for r in rows])
+    reg_m = np.array([1.0 - es[(r["M"], r["N"])][tuple(r["model"])] / r["best_gflops"] for r in rows])
+    fl = np.array([tq.flops(r["M"], r["N"]) for r in rows])
+    rep = {
+        "train_rows": int(len(y)), "train_seconds": t_train, "final_losses": losses,
+        "pairs": [list(p) for p in pairs], "preselected_fallback_pairs": [list(p) for p in ps],
+        "n_test": len(rows), "fallback_rate": float(np.mean([r["fallback"] for r in rows])),
+        "regret_mean": float(reg.mean()), "regret_max": float(reg.max()),
+        "regret_model_only_mean": float(reg_m.mean()),
+        "regret_table_only_mean": float(np.nanmean(reg_t)),
+        "regret_table_only_max": float(np.nanmax(reg_t)),
+        "within_3pct": float(np.mean(reg <= 0.03)),
+        "flops_weighted_regret": float(np.sum(reg * fl) / np.sum(fl)),
+        "flops_weighted_regret_table_only": float(np.nansum(reg_t * fl) / np.sum(fl)),
+        "choose_ms_mean": 1e3 * t_choose / len(rows),
+        "rows": rows,
+    }
+    log("mlp: regret mean %.4f max %.4f (model only %.4f, table only %.4f), fallback %.2f" %
+        (rep["regret_mean"], rep["regret_max"], rep["regret_model_only_mean"],
+         rep["regret_table_only_mean"], rep["fallback_rate"]))
+    with open(os.path.join(out_dir, "mlp_report.json"), "w") as f:
+        json.dump(rep, f, indent=1)
+    with open(os.path.join(out_dir, "mlp_model.json"), "w") as f:
+        json.dump({"params": params.tolist(), "fmean": fmean.tolist(), "fstd": fstd.tolist(),
+                   "ymean": ymean, "ystd": ystd, "cand": cand.tolist()}, f)
+    return rep
+
+
+def _lib_set_model(params, nmodels, fmean, fstd, ymean, ystd, cand):
+    import ctypes
+    from . import _lib
+    F = ctypes.POINTER(ctypes.c_float)
+    fm = np.ascontiguousarray(fmean, dtype=np.float32)
+    fs = np.ascontiguousarray(fstd, dtype=np.float32)
+    c = np.ascontiguousarray(cand, dtype=np.int32)
+    if nmodels == 0:
+        return _lib.lib().qr_tune_set_model(None, 0, None, None, 0.0, 1.0, None, 0)
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    return _lib.lib().qr_tune_set_model(p.ctypes.data_as(F), nmodels, fm.ctypes.data_as(F),
+                                        fs.ctypes.data_as(F), ymean, ystd,
+                                        c.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(c) // 2)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("what", choices=["batched", "batched-tune", "sweep", "tune", "ship", "collect-train",
+                                     "collect-heldout", "mlp"])
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--db", default=None, help="JSON measurement database (read and extended)")
+    ap.add_argument("--budget", type=float, default=600.0, help="seconds of measuring (collect)")
+    a = ap.parse_args(argv)
+    os.makedirs(a.out, exist_ok=True)
+    if a.what == "ship":
+        ship_table(a.out, os.path.join(TUNING, "decision_table.txt"))
+        return 0
+    import torch
+    torch.cuda.set_device(0)
+    db = a.db or os.path.join(a.out, "measurements.json")
+    if a.what == "batched":
+        batched(a.out)
+    elif a.what == "batched-tune":
+        batched_tune(a.out, db)
+    elif a.what == "sweep":
+        sweep(a.out, db)
+    elif a.what == "tune":
+        tune(a.out, db)
+    elif a.what in ("collect-train", "collect-heldout"):
+        done = collect(db, a.what.split("-")[1], a.budget)
+        log("collect %s: %s" % (a.what, "complete" if done else "budget reached"))
+    else:
+        mlp(a.out, db)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -105,7 +105,40 @@ def heuristic2(step1, k=8):
     return [(hull[i][0], hull[i][1]) for i in sorted(set(chosen))]
 
 
-HEURISTICS = {0: heuristic0, 1: heuristic1, 2: heuristic2}
+def relaxed_property1(step1, nbs, tol=0.1, k=8):
+    """For each tile order in `nbs`, every IB whose kernel rate is within
+    `tol` of that order's best IB (Property 1 keeps only the best), at most
+    k pairs in total, the fastest first within each order."""
+    by_nb = {}
+    for (nb, ib), g in step1.items():
+        by_nb.setdefault(nb, []).append((g, ib))
+    lists = []
+    for nb in nbs:
+        cand = sorted(by_nb.get(nb, []), key=lambda t: (-t[0], t[1]))
+        if not cand:
+            continue
+        top = cand[0][0]
+        lists.append([(nb, ib) for g, ib in cand if g >= (1.0 - tol) * top])
+    out = []
+    depth = 0
+    while len(out) < k and any(depth < len(l) for l in lists):
+        for l in lists:
+            if depth < len(l) and len(out) < k:
+                out.append(l[depth])
+        depth += 1
+    return sorted(out)
+
+
+def heuristic2_relaxed(step1, k=8, tol=0.1):
+    """GPU adaptation: the tile orders Heuristic 2 selects, each with every
+    inner block whose DSSRFB rate is within `tol` of its best. On the GPU
+    the inner block also sets the latency of the panel kernels on the
+    critical path, which the DSSRFB benchmark does not see, so Property 1's
+    single IB per NB is too strict there."""
+    return relaxed_property1(step1, [nb for nb, _ in heuristic2(step1, k)], tol, k)
+
+
+HEURISTICS = {0: heuristic0, 1: heuristic1, 2: heuristic2, "2r": heuristic2_relaxed}
 
 
 def preselect(step1, heuristic=2, k=8):

@@ -35,7 +35,9 @@ class Measurer:
     warm-up, each on a fresh copy of the same seeded input), with a JSON
     cache keyed by (kind, M, N, NB, IB, batch)."""
 
-    def __init__(self, db_path=None, reps=6, seed=0):
+    def __init__(self, db_path=None, reps=6, seed=0, verbose=True, offline=False):
+        self.verbose = verbose
+        self.offline = offline  # serve from the database only (no device)
         self.db_path = db_path
         self.reps = reps
         self.seed = seed
@@ -78,6 +80,8 @@ class Measurer:
         if k in self.db:
             r = self.db[k]
             return r["gflops"], r["seconds"]
+        if self.offline:
+            raise KeyError("not measured: " + k)
         import torch
         import paper_1102_5328_amd as tq
         reps = reps or self.reps
@@ -102,6 +106,9 @@ class Measurer:
         med = S2.median(g)
         self.db[k] = {"gflops": med, "max": max(g), "runs": g, "seconds": sec, "M": M, "N": N,
                       "nb": nb, "ib": ib, "batch": 1, "kind": kind}
+        if self.verbose:
+            print("measured %s %dx%d nb=%d ib=%d: %.1f GFLOP/s (%.2f s)" % (kind, M, N, nb, ib, med, sec),
+                  flush=True)
         del A, T
         return med, sec
 
@@ -131,13 +138,16 @@ TEST_SHAPES = [("normal", 65536, 256), ("normal", 65536, 1024), ("normal", 16384
                ("normal", 24000, 3000)]
 
 
-def tune_search(measurer, out_dir, pairs=None, heuristics_=(0, 1, 2), k=8, log=print):
+def tune_search(measurer, out_dir, pairs=None, heuristics_=(0, 1, 2, "2r"), k=8, log=print,
+                step1=None):
     """Pruned search (Step 1 -> heuristic -> Step 2 PS / PSPAYG) against the
     exhaustive search over the same candidates, on on-grid and off-grid test
-    shapes; writes the decision tables and a JSON report."""
+    shapes; writes the decision tables and a JSON report. step1 = (rates,
+    seconds) reuses a Step-1 table instead of running the kernel benchmark
+    (with an offline measurer the whole analysis replays recorded runs)."""
     import paper_1102_5328_amd as tq
     pairs = pairs or config2_pairs()
-    s1, t_step1 = step1_gpu(pairs)
+    s1, t_step1 = step1 if step1 is not None else step1_gpu(pairs)
     log("step1 %.1f s: %s" % (t_step1, {"%dx%d" % p: round(v, 1) for p, v in s1.items()}))
     meas = lambda M, N, nb, ib: measurer.measure(M, N, nb, ib)
     report = {"pairs": pairs, "step1_seconds": t_step1,
@@ -150,6 +160,13 @@ def tune_search(measurer, out_dir, pairs=None, heuristics_=(0, 1, 2), k=8, log=p
         es[(kind, M, N)] = (best, res[best][0], {p: v[0] for p, v in res.items()})
         log("ES %s %dx%d: best %s %.1f GFLOP/s" % (kind, M, N, best, res[best][0]))
         measurer.save()
+    # Exhaustive search over the size grid: its decisions and its tuning time
+    # (the sum of the original runs' durations), the Table 1 analog.
+    es_table, t_es = S2.step2(STEP2_GRID, pairs, meas, payg=False)
+    measurer.save()
+    S2.write_table(os.path.join(out_dir, "decision_table_es.txt"), S2.decisions(es_table),
+                   comment="exhaustive search")
+    report["tuning_seconds"] = {"ES": t_es}
     for h in heuristics_:
         ps = H.preselect(s1, h, k)
         entry = {"PS": ps}
@@ -158,8 +175,8 @@ def tune_search(measurer, out_dir, pairs=None, heuristics_=(0, 1, 2), k=8, log=p
             measurer.save()
             dec = S2.decisions(table)
             name = "PSPAYG" if payg else "PS"
-            path = os.path.join(out_dir, "decision_table_h%d_%s.txt" % (h, name.lower()))
-            S2.write_table(path, dec, comment="heuristic %d, %s" % (h, name))
+            path = os.path.join(out_dir, "decision_table_h%s_%s.txt" % (h, name.lower()))
+            S2.write_table(path, dec, comment="heuristic %s, %s" % (h, name))
             tq.tune_load(path)
             chosen, got, ref = [], [], []
             for kind, M, N in TEST_SHAPES:
@@ -171,10 +188,11 @@ def tune_search(measurer, out_dir, pairs=None, heuristics_=(0, 1, 2), k=8, log=p
                 got.append(g)
                 ref.append(es[(kind, M, N)][1])
             avg, opt, pct = S2.summary(got, ref)
+            report["tuning_seconds"]["H%s_%s" % (h, name)] = t_step1 + t2
             entry[name] = {"step2_seconds": t2, "avg_pct_of_ES": avg, "optimum": opt,
                            "n": len(got), "pct": pct, "chosen": chosen,
                            "table": {"%dx%d" % s: [d[0], d[1], d[2]] for s, d in dec.items()}}
-            log("H%d %s: step2 %.1f s, avg %.2f%% of ES, optimum %d/%d" % (h, name, t2, avg, opt, len(got)))
+            log("H%s %s: step2 %.1f s, avg %.2f%% of ES, optimum %d/%d" % (h, name, t2, avg, opt, len(got)))
         avg, opt, _ = S2.summary([c[5] for c in entry["PSPAYG"]["chosen"]],
                                  [c[5] for c in entry["PS"]["chosen"]])
         entry["PSPAYG_over_PS"] = {"avg": avg, "optimum": opt}
