@@ -17,6 +17,33 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (matrix and vector)
+KERNEL_SRC = os.path.join(HERE, "paper_1102_5328_amd", "csrc", "tileqr_device.hip")
+TRAFFIC = os.path.join(HERE, "profiles", "traffic.txt")
+
+
+def kernel_source_hash():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(N, nb, ib):
+    """HBM bytes per launch of the persistent kernel from the rocprofv3
+    counter runs recorded in profiles/traffic.txt (FETCH_SIZE and WRITE_SIZE,
+    each scaled by the same counter's reading for a device copy of known
+    size), if they were taken on this kernel source and configuration; else
+    None."""
+    if not os.path.exists(TRAFFIC):
+        return None
+    h = kernel_source_hash()
+    with open(TRAFFIC) as f:
+        for line in f:
+            w = dict(x.split("=", 1) for x in line.split() if "=" in x)
+            if (w.get("kernel") == "tq_persistent" and w.get("src") == h and
+                    int(w.get("N", -1)) == N and int(w.get("NB", -1)) == nb and
+                    int(w.get("IB", -1)) == ib):
+                return float(w["bytes"])
+    return None
 
 
 def parse():
@@ -111,6 +138,7 @@ def main():
     dt = time.perf_counter() - t0
     tq.sync()
     kern_ms = sum(e0.elapsed_time(e1) for e0, e1 in evs) / args.steps
+    traffic = measured_traffic(N, nb, ib)
     ms_per_step = dt * 1e3 / args.steps
     flops = tq.flops(N, N)
     value = flops / (ms_per_step * 1e-3) / 1e9
@@ -133,9 +161,11 @@ def main():
         "pct_fp64_peak": round(100.0 * value / (PEAK_FP64_TFLOPS * 1e3), 2),
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3),
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
                      "kernel": "tq_persistent (whole DAG, one launch)",
-                     "kernel_ms": round(kern_ms, 3)},
+                     "kernel_ms": round(kern_ms, 3),
+                     "hbm_GBps": (round(traffic / (kern_ms * 1e-3) / 1e9, 1)
+                                  if traffic else None)},
     }
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(A0, args.cpu_seconds)
