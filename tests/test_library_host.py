@@ -229,3 +229,25 @@ def test_tune_load_rejects_malformed(lib, tmp_path):
     assert lib.qr_tune_load(str(p).encode()) == 7
     p.write_text("garbage\n")
     assert lib.qr_tune_load(str(p).encode()) == 7
+
+
+def test_shipped_decision_table(lib):
+    """The table the benchmark loads parses, and qr_tune answers from it:
+    the measured best at 16384^2, and a batch-class entry for a matrix of
+    the 2000-matrix batch."""
+    path = os.path.join(ROOT, "paper_1102_5328_amd", "tuning", "decision_table.txt")
+    tq.tune_load(path)
+    try:
+        entries = {}
+        for line in open(path):
+            w = line.split()
+            if w and w[0] == "entry":
+                entries[(int(w[1]), int(w[2]), int(w[3]))] = (int(w[4]), int(w[5]))
+        assert tq.tune(16384, 16384, 1)[:2] == entries[(16384, 16384, 1)]
+        assert tq.tune(16384, 16384, 1)[2] == 1
+        batch = [k for k in entries if k[2] > 1]
+        assert batch
+        m, n, b = batch[0]
+        assert tq.tune(m, n, b)[:2] == entries[(m, n, b)]
+    finally:
+        tq.tune_load(os.devnull)
