@@ -167,7 +167,9 @@ int qr_tune_load(const char *path);
  * qr_tune. params (host): nmodels x 8769 floats (layout of qr_mlp_forward);
  * feat_mean/feat_std (host, 5 each) standardise the features, the model
  * predicts (log GFLOP/s - y_mean) / y_std; cand (host, 2*ncand ints) lists
- * the (NB, IB) candidates. Errors: -1 nmodels, -2 params, -6 cand/ncand. */
+ * the (NB, IB) candidates (each a valid tiling). Errors: -1 nmodels outside
+ * [0, 64], -2 params null, -3 feat_mean null, -4 feat_std null or not
+ * positive, -7 cand null, ncand outside [1, 4096] or an invalid pair. */
 int qr_tune_set_model(const float *params, int nmodels, const float *feat_mean,
                       const float *feat_std, float y_mean, float y_std, const int *cand, int ncand);
 

@@ -316,9 +316,7 @@ struct ModelState {
   std::vector<float> params;
   float fmean[5], fstd[5];
   float ymean = 0, ystd = 1;
-  std::vector<int> cand;  // pairs
-  float *d_params = nullptr, *d_X = nullptr, *d_y = nullptr;
-  int dev = -1;
+  std::vector<int> cand;  // (NB, IB) pairs
 };
 ModelState g_model;
 
@@ -696,14 +694,19 @@ int qr_tune_set_model(const float *params, int nmodels, const float *feat_mean,
                       const float *feat_std, float y_mean, float y_std, const int *cand,
                       int ncand) {
   if (nmodels < 0 || nmodels > 64) return -1;
+  if (nmodels > 0) {
+    if (!params) return -2;
+    if (!feat_mean) return -3;
+    if (!feat_std) return -4;
+    for (int i = 0; i < 5; ++i)
+      if (!(feat_std[i] > 0.f)) return -4;
+    if (!cand || ncand < 1 || ncand > 4096) return -7;
+    for (int c = 0; c < ncand; ++c)
+      if (!nb_ok(cand[2 * c]) || cand[2 * c + 1] < 1 || cand[2 * c + 1] > cand[2 * c]) return -7;
+  }
   std::lock_guard<std::mutex> lk(g_mu);
-  if (g_model.d_params) hipFree(g_model.d_params);
-  if (g_model.d_X) hipFree(g_model.d_X);
-  if (g_model.d_y) hipFree(g_model.d_y);
   g_model = ModelState();
   if (nmodels == 0) return 0;
-  if (!params || !feat_mean || !feat_std) return -2;
-  if (!cand || ncand < 1 || ncand > 4096) return -6;
   g_model.nmodels = nmodels;
   g_model.params.assign(params, params + (size_t)nmodels * TQ_MLP_NPARAM);
   std::memcpy(g_model.fmean, feat_mean, sizeof(float) * 5);

@@ -357,7 +357,9 @@ def mlp(out_dir, db):
     rep_path = os.path.join(TUNING, "tuning_report.json")
     if os.path.exists(rep_path):
         with open(rep_path) as f:
-            ps = [tuple(p) for p in json.load(f)["heuristics"]["2"]["PS"]]
+            heur = json.load(f)["heuristics"]
+        # The pre-selection of the shipped heuristic (the GPU variant when present).
+        ps = [tuple(p) for p in heur.get("2r", heur.get("2"))["PS"]]
     ps = ps or pairs
     rows = []
     t_choose = 0.0

@@ -251,3 +251,25 @@ def test_shipped_decision_table(lib):
         assert tq.tune(m, n, b)[:2] == entries[(m, n, b)]
     finally:
         tq.tune_load(os.devnull)
+
+
+def test_tune_set_model_argument_errors(lib):
+    import numpy as np
+    F = ctypes.POINTER(ctypes.c_float)
+    I = ctypes.POINTER(ctypes.c_int)
+    p = np.zeros(8769, np.float32)
+    fm = np.zeros(5, np.float32)
+    fs = np.ones(5, np.float32)
+    good = np.array([64, 16, 128, 32], np.int32)
+    bad = np.array([64, 16, 128, 200], np.int32)
+    f = lib.qr_tune_set_model
+    P = lambda a: a.ctypes.data_as(F)
+    assert f(P(p), 65, P(fm), P(fs), 0.0, 1.0, good.ctypes.data_as(I), 2) == -1
+    assert f(None, 1, P(fm), P(fs), 0.0, 1.0, good.ctypes.data_as(I), 2) == -2
+    assert f(P(p), 1, None, P(fs), 0.0, 1.0, good.ctypes.data_as(I), 2) == -3
+    fz = fs.copy()
+    fz[3] = 0.0
+    assert f(P(p), 1, P(fm), P(fz), 0.0, 1.0, good.ctypes.data_as(I), 2) == -4
+    assert f(P(p), 1, P(fm), P(fs), 0.0, 1.0, bad.ctypes.data_as(I), 2) == -7
+    assert f(P(p), 1, P(fm), P(fs), 0.0, 1.0, None, 2) == -7
+    assert f(None, 0, None, None, 0.0, 1.0, None, 0) == 0
