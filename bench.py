@@ -46,6 +46,28 @@ def measured_traffic(N, nb, ib):
     return None
 
 
+def tuned_vs_exhaustive(N, nb, ib):
+    """GFLOP/s of the chosen (NB, IB) as a percentage of the exhaustive
+    search's best at this size, from the tuner's recorded runs (None when the
+    size was not searched exhaustively)."""
+    import json
+    path = os.path.join(HERE, "paper_1102_5328_amd", "tuning", "measurements.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        db = json.load(f)
+    from paper_1102_5328_amd.tuner.runner import config2_pairs
+    rates = {}
+    for p in config2_pairs():
+        r = db.get("normal:%d:%d:%d:%d:1" % (N, N, p[0], p[1]))
+        if r is None:
+            return None
+        rates[p] = r["gflops"]
+    if (nb, ib) not in rates:
+        return None
+    return round(100.0 * rates[(nb, ib)] / max(rates.values()), 2)
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -159,6 +181,7 @@ def main():
         "config": {"workload": "tile Householder QR of one %dx%d FP64 N(0,1) matrix" % (N, N),
                    "M": N, "N": N, "NB": nb, "IB": ib, "tiling_source": src},
         "pct_fp64_peak": round(100.0 * value / (PEAK_FP64_TFLOPS * 1e3), 2),
+        "tuned_vs_exhaustive_pct": tuned_vs_exhaustive(N, nb, ib),
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3),
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
