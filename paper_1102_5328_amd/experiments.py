@@ -336,68 +336,88 @@ def collect(db, which, budget_s, reps=2):
     return done
 
 
-def mlp(out_dir, db):
-    """Trains the ensemble on the database's timings and evaluates it on the
-    held-out shapes (which must all have been measured)."""
-    import paper_1102_5328_amd as tq
+def heldout_es(db):
+    """{(M, N): {pair: median GFLOP/s}} of the exhaustive search on the
+    held-out shapes (every pair must have been measured)."""
     pairs = R.config2_pairs()
-    meas = R.Measurer(db)
     _, test_shapes = _shape_sets()
-    es = {}
-    for (M, N) in test_shapes:
-        es[(M, N)] = {p: meas.db[R.Measurer.key("heldout", M, N, p[0], p[1])]["gflops"]
-                      for p in pairs}
-    X, y = _training_rows(meas.db)
-    log("training rows: %d" % len(y))
-    params, fmean, fstd, ymean, ystd, losses, t_train = train_ensemble(X, y)
-    cand = np.array(pairs, dtype=np.int32).reshape(-1)
-    table = os.path.join(TUNING, "decision_table.txt")
-    tq.tune_load(table if os.path.exists(table) else os.devnull)
-    ps = None
+    return {(M, N): {p: db[R.Measurer.key("heldout", M, N, p[0], p[1])]["gflops"] for p in pairs}
+            for (M, N) in test_shapes}
+
+
+def shipped_preselection():
+    """The pre-selected pairs of the shipped heuristic (the GPU variant when
+    the tuning report has it), the fallback search's candidates."""
     rep_path = os.path.join(TUNING, "tuning_report.json")
     if os.path.exists(rep_path):
         with open(rep_path) as f:
             heur = json.load(f)["heuristics"]
-        # The pre-selection of the shipped heuristic (the GPU variant when present).
-        ps = [tuple(p) for p in heur.get("2r", heur.get("2"))["PS"]]
-    ps = ps or pairs
+        return [tuple(p) for p in heur.get("2r", heur.get("2"))["preselected"]]
+    return R.config2_pairs()
+
+
+def evaluate(es, model, table=None, ps=None):
+    """Regret on the held-out shapes of three ways of choosing (NB, IB):
+    the model with fallback (ensemble spread > 5 %: the pruned search on the
+    shape, i.e. the best pre-selected pair), the model alone, and the
+    decision table alone. model = (params, fmean, fstd, ymean, ystd)."""
+    import paper_1102_5328_amd as tq
+    pairs = R.config2_pairs()
+    cand = np.array(pairs, dtype=np.int32).reshape(-1)
+    params, fmean, fstd, ymean, ystd = model
+    table = table or os.path.join(TUNING, "decision_table.txt")
+    tq.tune_load(table if os.path.exists(table) else os.devnull)
+    ps = ps or shipped_preselection()
     rows = []
     t_choose = 0.0
-    for (M, N) in test_shapes:
-        tq.check(_lib_set_model(None, 0, fmean, fstd, ymean, ystd, cand), "model off")
-        tnb, tib, _ = tq.tune(M, N, 1)
-        tq.check(_lib_set_model(params, len(params), fmean, fstd, ymean, ystd, cand), "model on")
-        t0 = time.perf_counter()
-        mnb, mib, src = tq.tune(M, N, 1)
-        t_choose += time.perf_counter() - t0
-        best = max(es[(M, N)], key=lambda p: es[(M, N)][p])
-        pbest = es[(M, N)][best]
-        fallback = bool(src & 8)
-        # Fallback: the pruned search on this shape, i.e. the best pre-selected pair.
-        choice = max(ps, key=lambda p: es[(M, N)][p]) if fallback else (mnb, mib)
-        rows.append({"M": M, "N": N, "best": list(best), "best_gflops": pbest,
-                     "model": [mnb, mib], "fallback": fallback, "chosen": list(choice),
-                     "chosen_gflops": es[(M, N)][choice], "table": [tnb, tib],
-                     "table_gflops": es[(M, N)].get((tnb, tib), float("nan"))})
-    _lib_set_model(None, 0, fmean, fstd, ymean, ystd, cand)
+    try:
+        for (M, N), rates in es.items():
+            tq.check(_lib_set_model(None, 0, fmean, fstd, ymean, ystd, cand), "model off")
+            tnb, tib, _ = tq.tune(M, N, 1)
+            tq.check(_lib_set_model(params, len(params), fmean, fstd, ymean, ystd, cand), "model on")
+            t0 = time.perf_counter()
+            mnb, mib, src = tq.tune(M, N, 1)
+            t_choose += time.perf_counter() - t0
+            best = max(rates, key=rates.get)
+            fallback = bool(src & 8)
+            choice = max(ps, key=lambda p: rates[p]) if fallback else (mnb, mib)
+            rows.append({"M": M, "N": N, "best": list(best), "best_gflops": rates[best],
+                         "model": [mnb, mib], "fallback": fallback, "chosen": list(choice),
+                         "chosen_gflops": rates[choice], "table": [tnb, tib],
+                         "table_gflops": rates.get((tnb, tib), float("nan")),
+                         "model_gflops": rates[(mnb, mib)]})
+    finally:
+        _lib_set_model(None, 0, fmean, fstd, ymean, ystd, cand)
     reg = np.array([1.0 - r["chosen_gflops"] / r["best_gflops"] for r in rows])
     reg_t = np.array([1.0 - r["table_gflops"] / r["best_gflops"] for r in rows])
-    reg_m = np.array([1.0 - es[(r["M"], r["N"])][tuple(r["model"])] / r["best_gflops"] for r in rows])
+    reg_m = np.array([1.0 - r["model_gflops"] / r["best_gflops"] for r in rows])
     fl = np.array([tq.flops(r["M"], r["N"]) for r in rows])
-    rep = {
-        "train_rows": int(len(y)), "train_seconds": t_train, "final_losses": losses,
-        "pairs": [list(p) for p in pairs], "preselected_fallback_pairs": [list(p) for p in ps],
+    return {
         "n_test": len(rows), "fallback_rate": float(np.mean([r["fallback"] for r in rows])),
+        "preselected_fallback_pairs": [list(p) for p in ps],
         "regret_mean": float(reg.mean()), "regret_max": float(reg.max()),
-        "regret_model_only_mean": float(reg_m.mean()),
+        "regret_model_only_mean": float(reg_m.mean()), "regret_model_only_max": float(reg_m.max()),
         "regret_table_only_mean": float(np.nanmean(reg_t)),
         "regret_table_only_max": float(np.nanmax(reg_t)),
         "within_3pct": float(np.mean(reg <= 0.03)),
         "flops_weighted_regret": float(np.sum(reg * fl) / np.sum(fl)),
         "flops_weighted_regret_table_only": float(np.nansum(reg_t * fl) / np.sum(fl)),
-        "choose_ms_mean": 1e3 * t_choose / len(rows),
+        "choose_ms_mean": 1e3 * t_choose / max(1, len(rows)),
         "rows": rows,
     }
+
+
+def mlp(out_dir, db):
+    """Trains the ensemble on the database's timings and evaluates it on the
+    held-out shapes (which must all have been measured)."""
+    meas = R.Measurer(db)
+    es = heldout_es(meas.db)
+    X, y = _training_rows(meas.db)
+    log("training rows: %d" % len(y))
+    params, fmean, fstd, ymean, ystd, losses, t_train = train_ensemble(X, y)
+    rep = {"train_rows": int(len(y)), "train_seconds": t_train, "final_losses": losses,
+           "pairs": [list(p) for p in R.config2_pairs()]}
+    rep.update(evaluate(es, (params, fmean, fstd, ymean, ystd)))
     log("mlp: regret mean %.4f max %.4f (model only %.4f, table only %.4f), fallback %.2f" %
         (rep["regret_mean"], rep["regret_max"], rep["regret_model_only_mean"],
          rep["regret_table_only_mean"], rep["fallback_rate"]))
@@ -405,7 +425,8 @@ def mlp(out_dir, db):
         json.dump(rep, f, indent=1)
     with open(os.path.join(out_dir, "mlp_model.json"), "w") as f:
         json.dump({"params": params.tolist(), "fmean": fmean.tolist(), "fstd": fstd.tolist(),
-                   "ymean": ymean, "ystd": ystd, "cand": cand.tolist()}, f)
+                   "ymean": ymean, "ystd": ystd,
+                   "cand": np.array(R.config2_pairs()).reshape(-1).tolist()}, f)
     return rep
 
 

@@ -169,7 +169,7 @@ def tune_search(measurer, out_dir, pairs=None, heuristics_=(0, 1, 2, "2r"), k=8,
     report["tuning_seconds"] = {"ES": t_es}
     for h in heuristics_:
         ps = H.preselect(s1, h, k)
-        entry = {"PS": ps}
+        entry = {"preselected": ps}
         for payg in (False, True):
             table, t2 = S2.step2(STEP2_GRID, ps, meas, payg=payg)
             measurer.save()
