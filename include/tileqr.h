@@ -71,7 +71,8 @@ int64_t qr_T_size(int64_t M, int64_t N, int NB, int IB);
  *      (i, k), i > k, the full vectors of DTSQRT.
  *  NB  tile order, 16 <= NB <= 512; IB inner block, 1 <= IB <= NB (IB need
  *      not divide NB: the last block of a tile is narrower). NB = 0 or IB = 0:
- *      taken from qr_tune(M, N, 1).
+ *      taken from qr_tune(M, N, 1). In this build the tile classes above
+ *      NB = 128 are switched off and return TILEQR_ERR_DISABLED.
  *  T   (out, device, qr_T_size(M, N, NB, IB) doubles): the T factors.
  * One persistent kernel runs the whole DAG; the dependency counters and the
  * task order are library state, so calls on the same device must not
@@ -152,7 +153,8 @@ int qr_ssrfb_bench(int NB, int IB, int calls, int workers, double *seconds);
  * the learned cost model if one is loaded and confident, then the decision
  * table's nearest benchmarked configuration (Section 6.1: nearest in
  * log M, log N, log batch; ties to the larger size), else the install
- * default (NB=128, IB=32). *source: 0 default, 1 table, 2 model, 3 env;
+ * default (NB=128, IB=32, or the table's "default" line). *source: 0
+ * default, 1 table, 2 model, 3 env;
  * +8 when the model was consulted but its ensemble spread exceeded 5 %
  * (the caller should run the pruned search for this shape).
  * Errors: -1 M < 0, -2 N < 0, -3 batch < 1, -4 NB null, -5 IB null. */
