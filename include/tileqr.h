@@ -156,7 +156,9 @@ int qr_ssrfb_bench(int NB, int IB, int calls, int workers, double *seconds);
  * default (NB=128, IB=32, or the table's "default" line). *source: 0
  * default, 1 table, 2 model, 3 env;
  * +8 when the model was consulted but its ensemble spread exceeded 5 %
- * (the caller should run the pruned search for this shape).
+ * (the caller should run the pruned search for this shape). The spread is
+ * the largest loss, against its own best candidate, that any model of the
+ * ensemble predicts for the ensemble-mean choice.
  * Errors: -1 M < 0, -2 N < 0, -3 batch < 1, -4 NB null, -5 IB null. */
 int qr_tune(int64_t M, int64_t N, int64_t batch, int *NB, int *IB, int *source);
 

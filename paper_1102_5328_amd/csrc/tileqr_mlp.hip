@@ -395,22 +395,25 @@ int tq_mlp_choose(const float *params_host, int nmodels, const float *fmean, con
   std::vector<float> y((size_t)ncand * nmodels);
   if (hipMemcpy(y.data(), d_y, sizeof(float) * y.size(), hipMemcpyDeviceToHost) != hipSuccess)
     return TILEQR_ERR_HIP;
+  // Choice: the candidate with the best ensemble-mean prediction. Spread:
+  // the largest loss any member predicts for that choice against its own
+  // best candidate, max_m (1 - g_m(choice) / max_c g_m(c)); members that
+  // agree on the ranking give 0 even when their absolute rates differ.
+  std::vector<double> g((size_t)ncand * nmodels), mean(ncand, 0.0);
+  for (int m = 0; m < nmodels; ++m)
+    for (int c = 0; c < ncand; ++c) {
+      g[(size_t)m * ncand + c] = std::exp((double)y[(size_t)m * ncand + c] * ystd + ymean);
+      mean[c] += g[(size_t)m * ncand + c] / nmodels;
+    }
   int best = 0;
-  double bestv = -1e300, bestspread = 0.0;
-  for (int c = 0; c < ncand; ++c) {
-    double mean = 0.0, mn = 1e300, mx = -1e300;
-    for (int m = 0; m < nmodels; ++m) {
-      const double g = std::exp((double)y[(size_t)m * ncand + c] * ystd + ymean);
-      mean += g;
-      mn = std::min(mn, g);
-      mx = std::max(mx, g);
-    }
-    mean /= nmodels;
-    if (mean > bestv) {
-      bestv = mean;
-      best = c;
-      bestspread = mean > 0 ? (mx - mn) / mean : 1.0;
-    }
+  for (int c = 1; c < ncand; ++c)
+    if (mean[c] > mean[best]) best = c;
+  double bestspread = 0.0;
+  for (int m = 0; m < nmodels; ++m) {
+    double top = 0.0;
+    for (int c = 0; c < ncand; ++c) top = std::max(top, g[(size_t)m * ncand + c]);
+    const double loss = top > 0.0 ? 1.0 - g[(size_t)m * ncand + best] / top : 1.0;
+    bestspread = std::max(bestspread, loss);
   }
   *nb = cand[2 * best];
   *ib = cand[2 * best + 1];

@@ -356,11 +356,32 @@ def shipped_preselection():
     return R.config2_pairs()
 
 
+def ensemble_predict(model, M, N, batch=1, pairs=None):
+    """Predicted GFLOP/s of every candidate pair for one shape by every
+    member of the ensemble (qr_mlp_forward on the device): nmodels x ncand."""
+    import torch
+    import paper_1102_5328_amd as tq
+    from . import _lib
+    params, fmean, fstd, ymean, ystd = model
+    pairs = pairs or R.config2_pairs()
+    X = np.array([features(M, N, nb, ib, batch) for nb, ib in pairs])
+    Xs = torch.from_numpy(((X - fmean) / fstd).astype(np.float32)).cuda()
+    P = torch.from_numpy(np.ascontiguousarray(params, dtype=np.float32)).cuda()
+    y = torch.empty((len(params), len(pairs)), dtype=torch.float32, device="cuda")
+    tq.check(_lib.lib().qr_mlp_forward(P.data_ptr(), len(params), Xs.data_ptr(), len(pairs),
+                                       y.data_ptr(), None), "qr_mlp_forward")
+    torch.cuda.synchronize()
+    return np.exp(y.cpu().numpy().astype(np.float64) * ystd + ymean)
+
+
 def evaluate(es, model, table=None, ps=None):
     """Regret on the held-out shapes of three ways of choosing (NB, IB):
-    the model with fallback (ensemble spread > 5 %: the pruned search on the
-    shape, i.e. the best pre-selected pair), the model alone, and the
-    decision table alone. model = (params, fmean, fstd, ymean, ystd)."""
+    qr_tune with the model installed (its choice, or the pruned search on the
+    shape, i.e. the best pre-selected pair, when it reports a spread above
+    5 %), the model alone (the ensemble-mean best), and the decision table
+    alone. model = (params, fmean, fstd, ymean, ystd). Also reports how often
+    the other reading of the spread, (max - min) / mean of the predicted
+    GFLOP/s at the chosen pair, would have fallen back."""
     import paper_1102_5328_amd as tq
     pairs = R.config2_pairs()
     cand = np.array(pairs, dtype=np.int32).reshape(-1)
@@ -376,16 +397,24 @@ def evaluate(es, model, table=None, ps=None):
             tnb, tib, _ = tq.tune(M, N, 1)
             tq.check(_lib_set_model(params, len(params), fmean, fstd, ymean, ystd, cand), "model on")
             t0 = time.perf_counter()
-            mnb, mib, src = tq.tune(M, N, 1)
+            qnb, qib, src = tq.tune(M, N, 1)
             t_choose += time.perf_counter() - t0
+            g = ensemble_predict(model, M, N, 1, pairs)
+            c = int(np.argmax(g.mean(0)))
+            own = pairs[c]
+            spread_range = float((g[:, c].max() - g[:, c].min()) / g[:, c].mean())
+            spread_loss = float(max(1.0 - g[k, c] / g[k].max() for k in range(len(g))))
             best = max(rates, key=rates.get)
             fallback = bool(src & 8)
-            choice = max(ps, key=lambda p: rates[p]) if fallback else (mnb, mib)
+            if not fallback:
+                assert (qnb, qib) == own, ((M, N), (qnb, qib), own)
+            choice = max(ps, key=lambda p: rates[p]) if fallback else own
             rows.append({"M": M, "N": N, "best": list(best), "best_gflops": rates[best],
-                         "model": [mnb, mib], "fallback": fallback, "chosen": list(choice),
+                         "model": list(own), "model_gflops": rates[own],
+                         "spread": spread_loss, "spread_range": spread_range,
+                         "fallback": fallback, "chosen": list(choice),
                          "chosen_gflops": rates[choice], "table": [tnb, tib],
-                         "table_gflops": rates.get((tnb, tib), float("nan")),
-                         "model_gflops": rates[(mnb, mib)]})
+                         "table_gflops": rates.get((tnb, tib), float("nan"))})
     finally:
         _lib_set_model(None, 0, fmean, fstd, ymean, ystd, cand)
     reg = np.array([1.0 - r["chosen_gflops"] / r["best_gflops"] for r in rows])
@@ -394,13 +423,17 @@ def evaluate(es, model, table=None, ps=None):
     fl = np.array([tq.flops(r["M"], r["N"]) for r in rows])
     return {
         "n_test": len(rows), "fallback_rate": float(np.mean([r["fallback"] for r in rows])),
+        "fallback_rate_range_reading": float(np.mean([r["spread_range"] > 0.05 for r in rows])),
         "preselected_fallback_pairs": [list(p) for p in ps],
         "regret_mean": float(reg.mean()), "regret_max": float(reg.max()),
         "regret_model_only_mean": float(reg_m.mean()), "regret_model_only_max": float(reg_m.max()),
         "regret_table_only_mean": float(np.nanmean(reg_t)),
         "regret_table_only_max": float(np.nanmax(reg_t)),
         "within_3pct": float(np.mean(reg <= 0.03)),
+        "within_3pct_model_only": float(np.mean(reg_m <= 0.03)),
+        "within_3pct_table_only": float(np.mean(reg_t <= 0.03)),
         "flops_weighted_regret": float(np.sum(reg * fl) / np.sum(fl)),
+        "flops_weighted_regret_model_only": float(np.sum(reg_m * fl) / np.sum(fl)),
         "flops_weighted_regret_table_only": float(np.nansum(reg_t * fl) / np.sum(fl)),
         "choose_ms_mean": 1e3 * t_choose / max(1, len(rows)),
         "rows": rows,
