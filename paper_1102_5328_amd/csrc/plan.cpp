@@ -56,44 +56,50 @@ void dag_tile_counts(int64_t M, int64_t N, int nb, int64_t counts[4]) {
 }
 
 double task_cost(const Task &t, const MatDesc &m) {
-  // Rough per-workgroup rates (ns units); only the relative sizes matter.
-  const double upd_rate = 120.0;   // flop/ns of one workgroup on LARFB/SSRFB
-  const double pan_rate = 60.0;    // flop/ns of the panel's blocked updates
-  const double col_lat = 1200.0;   // ns per Householder column in a panel
+  // Duration of one task on one workgroup (ns) with two workgroups per
+  // compute unit, fitted to task traces of the persistent kernel at NB = 64
+  // and NB = 128 under full load: a panel costs a latency per Householder
+  // column that grows with the rows it touches; an update strip costs a
+  // fixed latency (staging, barriers, dependency fences) plus its MFMA work.
+  // Only relative sizes matter: they set the list schedule's priorities.
+  const double g_col0 = 3280.0, g_row = 80.3;   // GEQRT: ns per column, + per row
+  const double t_col0 = 3460.0, t_row = 97.5;   // TSQRT
+  const double l_fix = 48000.0, l_rate = 0.066;  // LARFB: ns + ns per (rows*refl*cols)
+  const double s_fix = 94000.0, s_rate = 0.103;  // SSRFB
   int s = task_strip(t);
   switch (task_type(t)) {
     case TK_GEQRT: {
       double mb = tile_rows(m, t.k), nb = tile_cols(m, t.k);
       double kk = mb < nb ? mb : nb;
-      return kk * col_lat + 2.0 * mb * nb * kk / pan_rate;
+      return kk * (g_col0 + g_row * mb);
     }
     case TK_TSQRT: {
       double mb = tile_rows(m, t.i), nb = tile_cols(m, t.k);
-      return nb * col_lat + 2.0 * mb * nb * nb / pan_rate;
+      return nb * (t_col0 + t_row * mb);
     }
     case TK_LARFB: {
       double mb = tile_rows(m, t.k), nb = tile_cols(m, t.k);
       double c = tile_cols(m, t.j) - s * m.w;
       c = c < m.w ? c : m.w;
-      return 2000.0 + 2.0 * mb * nb * c / upd_rate;
+      return l_fix + l_rate * mb * nb * c;
     }
     case TK_SSRFB: {
       double mb = tile_rows(m, t.i), nb = tile_cols(m, t.k);
       double c = tile_cols(m, t.j) - s * m.w;
       c = c < m.w ? c : m.w;
-      return 2000.0 + 4.0 * mb * nb * c / upd_rate;
+      return s_fix + s_rate * mb * nb * c;
     }
     case TK_LARFB_B: {
       double mb = tile_rows(m, t.k), nb = tile_cols(m, t.k);
       double c = m.nrhs - s * m.w;
       c = c < m.w ? c : m.w;
-      return 2000.0 + 2.0 * mb * nb * c / upd_rate;
+      return l_fix + l_rate * mb * nb * c;
     }
     case TK_SSRFB_B: {
       double mb = tile_rows(m, t.i), nb = tile_cols(m, t.k);
       double c = m.nrhs - s * m.w;
       c = c < m.w ? c : m.w;
-      return 2000.0 + 4.0 * mb * nb * c / upd_rate;
+      return s_fix + s_rate * mb * nb * c;
     }
   }
   return 1.0;
