@@ -17,14 +17,20 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (matrix and vector)
-KERNEL_SRC = os.path.join(HERE, "paper_1102_5328_amd", "csrc", "tileqr_device.hip")
+# Sources whose change invalidates recorded counters: the kernels and the
+# host scheduler that orders their tasks.
+KERNEL_SRC = [os.path.join(HERE, "paper_1102_5328_amd", "csrc", f)
+              for f in ("tileqr_device.hip", "plan.cpp")]
 TRAFFIC = os.path.join(HERE, "profiles", "traffic.txt")
 
 
 def kernel_source_hash():
     import hashlib
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(N, nb, ib):
@@ -51,7 +57,7 @@ def tuned_vs_exhaustive(N, nb, ib):
     search's best at this size, from the tuner's recorded runs (None when the
     size was not searched exhaustively)."""
     import json
-    path = os.path.join(HERE, "paper_1102_5328_amd", "tuning", "measurements.json")
+    path = os.path.join(HERE, "paper_1102_5328_amd", "tuning", "tune_timings.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:

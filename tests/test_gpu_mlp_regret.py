@@ -12,7 +12,7 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-DB = os.path.join(os.path.dirname(HERE), "paper_1102_5328_amd", "tuning", "measurements.json")
+DB = os.path.join(os.path.dirname(HERE), "paper_1102_5328_amd", "tuning", "mlp_timings.json")
 
 
 def test_model_regret_against_exhaustive_search():
