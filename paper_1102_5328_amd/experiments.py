@@ -116,11 +116,14 @@ def _pow2_class(x):
 
 
 def batched_tune(out_dir, db, count=2000, seed=0, reps=3):
-    """Step 2 for the batch: the matrices are grouped in size classes
-    (M and N rounded up to powers of two); for each class, every enabled
-    (NB, IB) is timed on a batched launch of the class's matrices and the
-    fastest is recorded as a decision-table entry for (class M, class N,
-    batch count). Returns the entries."""
+    """Step 2 for the batch. The matrices are grouped in size classes (M and
+    N rounded up to powers of two); for each class, every enabled (NB, IB) is
+    timed on a batched launch of the class's matrices. One launch runs every
+    matrix in the register class of its largest tile order, so per-class
+    choices are then combined within each register class (NB <= 64, NB <= 128)
+    and, with every uniform pair, timed on the whole batch; the fastest
+    whole-batch assignment gives the decision-table entries (class M, class
+    N, batch count). Returns the entries."""
     import torch
     import paper_1102_5328_amd as tq
     shapes = inputs.batch_shapes(count, seed=seed)
@@ -131,6 +134,7 @@ def batched_tune(out_dir, db, count=2000, seed=0, reps=3):
     meas = R.Measurer(db)
     pairs = R.config2_pairs()
     entries = {}
+    per_class = {}
     t0 = time.perf_counter()
     for (cm, cn), idx in sorted(classes.items()):
         A0 = []
@@ -165,14 +169,55 @@ def batched_tune(out_dir, db, count=2000, seed=0, reps=3):
                                 "M": mg, "N": ng, "nb": nb, "ib": ib, "batch": count,
                                 "kind": "batched", "class": [cm, cn], "matrices": len(idx)}
             res[(nb, ib)] = meas.db[key]["gflops"]
+        per_class[(cm, cn)] = res
         best = max(res, key=lambda p: (res[p], -p[0]))
-        rec = meas.db["batched:%d:%d:%d:%d:%d" % (cm, cn, best[0], best[1], count)]
-        entries[(rec["M"], rec["N"])] = (best[0], best[1], res[best])
         log("batch class %dx%d (%d matrices): best %s %.1f GFLOP/s (%.0f s)" %
             (cm, cn, len(idx), best, res[best], time.perf_counter() - t0))
         meas.save()
+    # Whole-batch assignments: per-class best within each register class,
+    # and every uniform pair.
+    groups = {"nb<=64": [p for p in pairs if p[0] <= 64], "nb<=128": [p for p in pairs if p[0] > 64]}
+    cands = {}
+    for gname, gp in groups.items():
+        cands["per-class " + gname] = {c: max(gp, key=lambda p: (per_class[c][p], -p[0]))
+                                       for c in classes}
+    for p in pairs:
+        cands["uniform %d/%d" % p] = {c: p for c in classes}
+    A0 = []
+    for b in range(count):
+        d = tq.colmajor(*shapes[b])
+        d.copy_(torch.from_numpy(np.ascontiguousarray(mats[b].T)).t())
+        A0.append(d)
+    As = [tq.colmajor(*shapes[b]) for b in range(count)]
+    fl_all = sum(tq.flops(*sh) for sh in shapes)
+    whole = {}
+    for name, assign in cands.items():
+        til = [assign[(_pow2_class(m), _pow2_class(n))] for m, n in shapes]
+        Ts = [torch.empty(max(1, tq.T_size(*shapes[b], *til[b])), dtype=torch.float64,
+                          device="cuda") for b in range(count)]
+        nbs, ibs = [t[0] for t in til], [t[1] for t in til]
+        ts = []
+        for r in range(reps + 1):
+            for a, a0 in zip(As, A0):
+                a.copy_(a0)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            tq.factor_batched(As, nbs, ibs, Ts)
+            tq.sync()
+            ts.append(time.perf_counter() - t1)
+        whole[name] = fl_all / float(np.median(ts[1:])) / 1e9
+        log("whole batch, %s: %.1f GFLOP/s" % (name, whole[name]))
+        del Ts
+    pick = max(whole, key=whole.get)
+    log("whole batch: %s is fastest" % pick)
+    for (cm, cn), idx in classes.items():
+        nb, ib = cands[pick][(cm, cn)]
+        rec = meas.db["batched:%d:%d:%d:%d:%d" % (cm, cn, nb, ib, count)]
+        entries[(rec["M"], rec["N"])] = (nb, ib, per_class[(cm, cn)][(nb, ib)])
     with open(os.path.join(out_dir, "batched_tune.json"), "w") as f:
         json.dump({"%dx%d" % k: list(v) for k, v in entries.items()}, f, indent=1)
+    with open(os.path.join(out_dir, "batched_tune_whole.json"), "w") as f:
+        json.dump({"whole_batch_gflops": whole, "chosen": pick}, f, indent=1)
     return entries
 
 
