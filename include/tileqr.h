@@ -82,8 +82,10 @@ int qr_factor(double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, doub
               void *stream);
 
 /* B <- Q^T B with Q from qr_factor(A, M, N, lda, NB, IB, T). NB and IB must
- * be the ones the factorization used (V and T depend on them). B is M x nrhs
- * with ldb >= max(1, M); A and T are read only.
+ * be the ones the factorization used (V and T depend on them); 0 resolves
+ * through qr_tune(M, N, 1) as in qr_factor, which reproduces its choice as
+ * long as the decision table and model are unchanged in between. B is
+ * M x nrhs with ldb >= max(1, M); A and T are read only.
  * Errors: -1 A, -2 M, -3 N, -4 lda, -5 NB, -6 IB, -7 T, -8 B null,
  * -9 nrhs < 0, -10 ldb. */
 int qr_apply_Qt(const double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB,
