@@ -146,6 +146,16 @@ int qr_tile_task(int kind, double *A, int64_t M, int64_t N, int64_t lda, int NB,
  * -5 seconds null. */
 int qr_ssrfb_bench(int NB, int IB, int calls, int workers, double *seconds);
 
+/* Step 1 with cold caches (the flushed-cache timing of Section 5): the
+ * same DSSRFB per workgroup as qr_ssrfb_bench, but each of the `calls`
+ * calls in its own launch, preceded by a write over `flush_bytes` of scratch
+ * device memory (0 = none) that evicts the tiles from the L2 caches and the
+ * MALL; *seconds (host) sums the DSSRFB launches only. Errors: -1 NB, -2 IB,
+ * -3 calls, -4 workers, -5 flush_bytes outside [0, 64 GiB], -6 seconds
+ * null. */
+int qr_ssrfb_bench_flush(int NB, int IB, int calls, int workers, int64_t flush_bytes,
+                         double *seconds);
+
 /* ---------------------------------------------------------------------- */
 /* Tuning decision (Problem 2.1: instantaneous choice of (NB, IB))          */
 /* ---------------------------------------------------------------------- */

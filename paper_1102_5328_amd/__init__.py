@@ -15,7 +15,7 @@ from ._lib import TileQRError, check
 
 __all__ = [
     "colmajor", "T_size", "factor", "apply_Qt", "factor_batched", "factor_loop", "sync",
-    "tile_task", "ssrfb_bench", "tune", "tune_load", "flops", "flops_executed", "dag_counts",
+    "tile_task", "ssrfb_bench", "ssrfb_bench_flush", "tune", "tune_load", "flops", "flops_executed", "dag_counts",
     "plan_check", "plan_tasks", "TileQRError", "check",
 ]
 
@@ -144,6 +144,13 @@ def tile_task(kind, A, nb, ib, T, i, j, k, stream=None):
 def ssrfb_bench(nb, ib, calls=50, workers=0):
     sec = ctypes.c_double()
     check(_lib.lib().qr_ssrfb_bench(nb, ib, calls, workers, ctypes.byref(sec)), "qr_ssrfb_bench")
+    return sec.value
+
+
+def ssrfb_bench_flush(nb, ib, calls=50, workers=0, flush_bytes=1 << 30):
+    sec = ctypes.c_double()
+    check(_lib.lib().qr_ssrfb_bench_flush(nb, ib, calls, workers, flush_bytes, ctypes.byref(sec)),
+          "qr_ssrfb_bench_flush")
     return sec.value
 
 

@@ -36,6 +36,7 @@ SIGNATURES = {
     "qr_trace_fetch": (c_int, [c_i64p, c_i64, c_i64p]),
     "qr_tile_task": (c_int, [c_int, c_vp, c_i64, c_i64, c_i64, c_int, c_int, c_vp, c_int, c_int, c_int, c_vp]),
     "qr_ssrfb_bench": (c_int, [c_int, c_int, c_int, c_int, c_dblp]),
+    "qr_ssrfb_bench_flush": (c_int, [c_int, c_int, c_int, c_int, c_i64, c_dblp]),
     "qr_tune": (c_int, [c_i64, c_i64, c_i64, c_intp, c_intp, c_intp]),
     "qr_tune_load": (c_int, [ctypes.c_char_p]),
     "qr_tune_set_model": (c_int, [c_fltp, c_int, c_fltp, c_fltp, c_flt, c_flt, c_intp, c_int]),

@@ -652,6 +652,58 @@ int qr_ssrfb_bench(int NB, int IB, int calls, int workers, double *seconds) {
   return rc;
 }
 
+// Step 1 with cold caches: every call in its own launch, each preceded by a
+// write over `flush_bytes` of scratch memory (larger than the L2 caches and
+// the MALL together) that evicts the tiles; only the DSSRFB launches are
+// timed. The tiles are the same per workgroup as in qr_ssrfb_bench.
+int qr_ssrfb_bench_flush(int NB, int IB, int calls, int workers, int64_t flush_bytes,
+                         double *seconds) {
+  if (!nb_ok(NB)) return -1;
+  if (IB < 1 || IB > NB) return -2;
+  if (calls < 1) return -3;
+  if (workers < 0) return -4;
+  if (flush_bytes < 0 || flush_bytes > ((int64_t)64 << 30)) return -5;
+  if (!seconds) return -6;
+  if (!nb_enabled(NB)) return TILEQR_ERR_DISABLED;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DevState *ds;
+  int rc = dev_state(&ds);
+  if (rc) return rc;
+  const int grid = workers > 0 ? workers : ds->ncu;
+  const int64_t per = 3 * (int64_t)NB * NB + (int64_t)IB * NB;
+  const int64_t nflush = flush_bytes / 8;
+  double *buf = nullptr, *flush = nullptr;
+  if (hipMalloc(&buf, sizeof(double) * per * grid) != hipSuccess) return TILEQR_ERR_NOMEM;
+  if (nflush > 0 && hipMalloc(&flush, sizeof(double) * nflush) != hipSuccess) {
+    hipFree(buf);
+    return TILEQR_ERR_NOMEM;
+  }
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  double total = 0.0;
+  if (tq_launch_fill(buf, per * grid, 12345, 0.02, 0) != hipSuccess) rc = TILEQR_ERR_HIP;
+  for (int c = 0; c < calls && !rc; ++c) {
+    if (nflush > 0 && tq_launch_fill(flush, nflush, 777 + (uint64_t)c, 1.0, 0) != hipSuccess) {
+      rc = TILEQR_ERR_HIP;
+      break;
+    }
+    hipEventRecord(e0, 0);
+    if (tq_launch_ssrfb_bench(buf, NB, IB, 1, grid, 0) != hipSuccess) rc = TILEQR_ERR_HIP;
+    hipEventRecord(e1, 0);
+    if (hipEventSynchronize(e1) != hipSuccess) rc = TILEQR_ERR_HIP;
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    total += ms * 1e-3;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipFree(buf);
+  if (flush) hipFree(flush);
+  *seconds = total;
+  return rc;
+}
+
 // ------------------------------------------------------------------ tuning
 
 int qr_tune_load(const char *path) {

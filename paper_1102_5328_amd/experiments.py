@@ -276,6 +276,33 @@ def ship_table(tune_dir, out_path, heuristic="2r", batch_count=2000):
     return entries
 
 
+def step1_cold(out_dir, db, flush_bytes=1 << 30):
+    """Step 1 with warm and with cold caches, and what each pre-selects: the
+    Step-2 analysis of every heuristic is replayed from the recorded runs
+    (the database must hold every pair on the grid and the test shapes)."""
+    pairs = R.config2_pairs()
+    warm, t_warm = R.step1_gpu(pairs)
+    cold, t_cold = R.step1_gpu(pairs, flush_bytes=flush_bytes)
+    log("step1 warm (%.1f s): %s" % (t_warm, {"%d,%d" % p: round(v) for p, v in warm.items()}))
+    log("step1 cold (%.1f s): %s" % (t_cold, {"%d,%d" % p: round(v) for p, v in cold.items()}))
+    rep = {"flush_bytes": flush_bytes,
+           "step1_warm": {"%d,%d" % p: v for p, v in warm.items()}, "step1_warm_seconds": t_warm,
+           "step1_cold": {"%d,%d" % p: v for p, v in cold.items()}, "step1_cold_seconds": t_cold}
+    for name, s1, t1 in (("warm", warm, t_warm), ("cold", cold, t_cold)):
+        sub = os.path.join(out_dir, "step1_" + name)
+        os.makedirs(sub, exist_ok=True)
+        m = R.Measurer(db, offline=True, verbose=False)
+        r = R.tune_search(m, sub, step1=(s1, t1), log=log)
+        rep[name] = {h: {"preselected": e["preselected"],
+                         "PSPAYG_avg_pct_of_ES": e["PSPAYG"]["avg_pct_of_ES"],
+                         "PSPAYG_optimum": e["PSPAYG"]["optimum"],
+                         "PSPAYG_seconds": r["tuning_seconds"]["H%s_PSPAYG" % h]}
+                     for h, e in r["heuristics"].items()}
+    with open(os.path.join(out_dir, "step1_cold_report.json"), "w") as f:
+        json.dump(rep, f, indent=1)
+    return rep
+
+
 # -------------------------------------------------------------------- MLP
 
 NP = 8769
@@ -525,7 +552,8 @@ def _lib_set_model(params, nmodels, fmean, fstd, ymean, ystd, cand):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["batched", "batched-tune", "sweep", "tune", "ship", "collect-train",
+    ap.add_argument("what", choices=["batched", "batched-tune", "sweep", "tune", "step1-cold", "ship",
+                                     "collect-train",
                                      "collect-heldout", "mlp"])
     ap.add_argument("--out", required=True)
     ap.add_argument("--db", default=None, help="JSON measurement database (read and extended)")
@@ -546,6 +574,8 @@ def main(argv=None):
         sweep(a.out, db)
     elif a.what == "tune":
         tune(a.out, db)
+    elif a.what == "step1-cold":
+        step1_cold(a.out, db)
     elif a.what in ("collect-train", "collect-heldout"):
         done = collect(db, a.what.split("-")[1], a.budget)
         log("collect %s: %s" % (a.what, "complete" if done else "budget reached"))

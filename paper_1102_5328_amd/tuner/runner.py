@@ -113,16 +113,22 @@ class Measurer:
         return med, sec
 
 
-def step1_gpu(pairs, calls=50):
-    """Kernel benchmark of DSSRFB on every pair, one workgroup per CU, calls
-    timed together (No Flush). Returns ({pair: gflops}, seconds)."""
+def step1_gpu(pairs, calls=50, flush_bytes=0):
+    """Kernel benchmark of DSSRFB on every pair, one workgroup per CU. With
+    flush_bytes = 0 the calls are timed together on warm tiles (No Flush);
+    otherwise each call runs in its own launch after a write over
+    flush_bytes of scratch memory that evicts the tiles (cold caches).
+    Returns ({pair: gflops}, seconds)."""
     import paper_1102_5328_amd as tq
     import torch
     ncu = torch.cuda.get_device_properties(0).multi_processor_count
     out = {}
     t0 = time.perf_counter()
     for nb, ib in pairs:
-        sec = tq.ssrfb_bench(nb, ib, calls, 0)
+        if flush_bytes > 0:
+            sec = tq.ssrfb_bench_flush(nb, ib, calls, 0, flush_bytes)
+        else:
+            sec = tq.ssrfb_bench(nb, ib, calls, 0)
         out[(nb, ib)] = calls * ncu * 4.0 * nb ** 3 / sec / 1e9
     return out, time.perf_counter() - t0
 

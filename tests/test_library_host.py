@@ -86,6 +86,13 @@ def test_other_argument_errors(lib):
     assert lib.qr_ssrfb_bench(64, 16, 0, 0, ctypes.byref(sec)) == -3
     assert lib.qr_ssrfb_bench(64, 16, 1, -1, ctypes.byref(sec)) == -4
     assert lib.qr_ssrfb_bench(64, 16, 1, 0, None) == -5
+    f = lib.qr_ssrfb_bench_flush
+    assert f(8, 4, 1, 0, 0, ctypes.byref(sec)) == -1
+    assert f(64, 65, 1, 0, 0, ctypes.byref(sec)) == -2
+    assert f(64, 16, 0, 0, 0, ctypes.byref(sec)) == -3
+    assert f(64, 16, 1, -1, 0, ctypes.byref(sec)) == -4
+    assert f(64, 16, 1, 0, -8, ctypes.byref(sec)) == -5
+    assert f(64, 16, 1, 0, 0, None) == -6
     assert lib.qr_T_size(-1, 4, 64, 16) == -1
     assert lib.qr_T_size(4, -1, 64, 16) == -2
     assert lib.qr_T_size(4, 4, 0, 16) == -3
