@@ -54,14 +54,35 @@ def T_size(M, N, nb, ib):
     return n
 
 
+import os as _os
+
+SHIPPED_TABLE = _os.path.join(_os.path.dirname(_os.path.abspath(__file__)), "tuning",
+                              "decision_table.txt")
+_table_loaded = False
+
+
+def _ensure_table():
+    """Loads the shipped decision table once, unless the caller loaded one."""
+    global _table_loaded
+    if not _table_loaded:
+        _table_loaded = True
+        if _os.path.exists(SHIPPED_TABLE):
+            check(_lib.lib().qr_tune_load(SHIPPED_TABLE.encode()), "qr_tune_load")
+
+
 def tune(M, N, batch=1):
+    """(NB, IB, source) from qr_tune; the shipped decision table is loaded
+    on first use unless tune_load was called before."""
+    _ensure_table()
     nb, ib, src = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     check(_lib.lib().qr_tune(M, N, batch, ctypes.byref(nb), ctypes.byref(ib), ctypes.byref(src)), "qr_tune")
     return nb.value, ib.value, src.value
 
 
 def tune_load(path):
+    global _table_loaded
     check(_lib.lib().qr_tune_load(path.encode()), "qr_tune_load")
+    _table_loaded = True
 
 
 def factor(A, nb=0, ib=0, T=None, stream=None):
