@@ -110,6 +110,14 @@ int qr_factor_batched(double *const *A, const int64_t *M, const int64_t *N, cons
 int qr_factor_loop(double *const *A, const int64_t *M, const int64_t *N, const int64_t *lda,
                    int64_t count, const int *NB, const int *IB, double *const *T, void *stream);
 
+/* Sizes the persistent grid, and the schedule the host builds for it, for
+ * `cus` compute units (0 or the device's count: all of them) in the launches
+ * that follow: the setting for a stream created with a compute-unit mask
+ * (hipExtStreamCreateWithCUMask) of that many units, the analog of the core
+ * count of Sections 4-6. Errors: -1 cus < 0 or above the device's count;
+ * positive: no device. */
+int qr_set_compute_units(int cus);
+
 /* Waits for the stream, then returns (and clears) the first error the device
  * scheduler reported since the last call (TILEQR_ERR_WATCHDOG), or a HIP
  * error; 0 if none. */

@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import TileQRError, check
 
 __all__ = [
-    "colmajor", "T_size", "factor", "apply_Qt", "factor_batched", "factor_loop", "sync",
+    "colmajor", "T_size", "factor", "apply_Qt", "factor_batched", "factor_loop", "set_compute_units", "sync",
     "tile_task", "ssrfb_bench", "ssrfb_bench_flush", "tune", "tune_load", "flops", "flops_executed", "dag_counts",
     "plan_check", "plan_tasks", "TileQRError", "check",
 ]
@@ -136,6 +136,11 @@ def factor_loop(As, nbs, ibs, Ts, stream=None):
     check(_lib.lib().qr_factor_loop(ctypes.cast(a, ctypes.c_void_p), m, n, ld, len(As), nb, ib,
                                     ctypes.cast(t, ctypes.c_void_p), _stream(stream)),
           "qr_factor_loop")
+
+
+def set_compute_units(cus):
+    """Grid and schedule for `cus` compute units (0: all); see the header."""
+    check(_lib.lib().qr_set_compute_units(cus), "qr_set_compute_units")
 
 
 def sync(stream=None):

@@ -33,6 +33,7 @@ SIGNATURES = {
     "qr_factor_batched": (c_int, [c_vp, c_i64p, c_i64p, c_i64p, c_i64, c_intp, c_intp, c_vp, c_vp]),
     "qr_factor_loop": (c_int, [c_vp, c_i64p, c_i64p, c_i64p, c_i64, c_intp, c_intp, c_vp, c_vp]),
     "qr_sync": (c_int, [c_vp]),
+    "qr_set_compute_units": (c_int, [c_int]),
     "qr_trace_fetch": (c_int, [c_i64p, c_i64, c_i64p]),
     "qr_tile_task": (c_int, [c_int, c_vp, c_i64, c_i64, c_i64, c_int, c_int, c_vp, c_int, c_int, c_int, c_vp]),
     "qr_ssrfb_bench": (c_int, [c_int, c_int, c_int, c_int, c_dblp]),

@@ -87,13 +87,18 @@ struct Plan {
   }
 };
 
+// Compute units the persistent grid and its schedule are sized for (0: all
+// of the device); see qr_set_compute_units.
+int g_cu_limit = 0;
+
 struct PlanKey {
   int dev, apply, nb, ib;
   int64_t M, N, nrhs;
   uint64_t batch_hash;
+  int cus = g_cu_limit;
   bool operator<(const PlanKey &o) const {
-    return std::tie(dev, apply, nb, ib, M, N, nrhs, batch_hash) <
-           std::tie(o.dev, o.apply, o.nb, o.ib, o.M, o.N, o.nrhs, o.batch_hash);
+    return std::tie(dev, apply, nb, ib, M, N, nrhs, batch_hash, cus) <
+           std::tie(o.dev, o.apply, o.nb, o.ib, o.M, o.N, o.nrhs, o.batch_hash, o.cus);
   }
   bool operator==(const PlanKey &o) const { return !(*this < o) && !(o < *this); }
 };
@@ -143,7 +148,8 @@ int get_plan(const PlanKey &key, std::vector<MatDesc> mats, bool apply, const De
     lds = std::max(lds, (size_t)lds_plan(mbt, m.ib).doubles * 8);
   }
   int occ = tq_occupancy(mbt, lds);
-  int grid = std::max(1, ds.ncu * occ);
+  const int cus = (key.cus > 0 && key.cus < ds.ncu) ? key.cus : ds.ncu;
+  int grid = std::max(1, cus * occ);
   Plan *p = new Plan();
   p->mbt = mbt;
   p->lds = lds;
@@ -508,6 +514,17 @@ int qr_factor_loop(double *const *A, const int64_t *M, const int64_t *N, const i
     rc = factor_one(A[b], M[b], N[b], lda[b], nbs[b], ibs[b], T[b], (hipStream_t)stream, *ds);
     if (rc) return rc;
   }
+  return 0;
+}
+
+int qr_set_compute_units(int cus) {
+  if (cus < 0) return -1;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DevState *ds;
+  int rc = dev_state(&ds);
+  if (rc) return rc;
+  if (cus > ds->ncu) return -1;
+  g_cu_limit = cus == ds->ncu ? 0 : cus;
   return 0;
 }
 

@@ -303,6 +303,80 @@ def step1_cold(out_dir, db, flush_bytes=1 << 30):
     return rep
 
 
+def _cu_masked_stream(cus, ncu):
+    """A stream restricted to the first `cus` compute units
+    (hipExtStreamCreateWithCUMask of the HIP runtime torch loaded)."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    words = (ncu + 31) // 32
+    mask = (ctypes.c_uint32 * words)()
+    for c in range(cus):
+        mask[c // 32] |= 1 << (c % 32)
+    st = ctypes.c_void_p()
+    rc = hip.hipExtStreamCreateWithCUMask(ctypes.byref(st), ctypes.c_uint32(words), mask)
+    if rc != 0:
+        raise RuntimeError("hipExtStreamCreateWithCUMask failed: %d" % rc)
+    return hip, st
+
+
+def cu_scaling(out_dir, sizes=(4096, 8192, 16384), cus_list=(32, 64, 128, 256),
+               pairs=((64, 16), (96, 16), (128, 16), (128, 32)), reps=3):
+    """Strong scaling over compute units, the analog of the paper's core
+    count: the factorization on a stream masked to `cus` units, with the
+    grid and schedule sized for them, for a few (NB, IB) per size."""
+    import torch
+    import paper_1102_5328_amd as tq
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    out = {}
+    try:
+        for cus in cus_list:
+            tq.set_compute_units(cus)
+            hip, st = _cu_masked_stream(cus, ncu)
+            stream = torch.cuda.ExternalStream(st.value)
+            for N in sizes:
+                A0 = inputs.torch_normal(N, N, seed=0)
+                A = tq.colmajor(N, N)
+                res = {}
+                for nb, ib in pairs:
+                    T = torch.empty(tq.T_size(N, N, nb, ib), dtype=torch.float64, device="cuda")
+                    ts = []
+                    for r in range(reps + 1):
+                        A.copy_(A0)
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        tq.factor(A, nb, ib, T, stream=stream)
+                        tq.sync(stream)
+                        ts.append(time.perf_counter() - t0)
+                    g = tq.flops(N, N) / float(np.median(ts[1:])) / 1e9
+                    res["%d,%d" % (nb, ib)] = g
+                    log("cus=%d N=%d nb=%d ib=%d: %.1f GFLOP/s" % (cus, N, nb, ib, g))
+                    del T
+                out.setdefault(str(cus), {})[str(N)] = res
+                del A, A0
+            torch.cuda.synchronize()
+            hip.hipStreamDestroy(st)
+    finally:
+        tq.set_compute_units(0)
+    summary = {}
+    for N in sizes:
+        row = {}
+        for cus in cus_list:
+            r = out[str(cus)][str(N)]
+            best = max(r, key=r.get)
+            row[str(cus)] = {"best": best, "gflops": r[best]}
+        base = row[str(cus_list[0])]["gflops"]
+        for cus in cus_list:
+            row[str(cus)]["speedup_vs_%d" % cus_list[0]] = row[str(cus)]["gflops"] / base
+            row[str(cus)]["efficiency"] = (row[str(cus)]["gflops"] / base) / (cus / cus_list[0])
+        summary[str(N)] = row
+    rep = {"cus": list(cus_list), "sizes": list(sizes), "pairs": [list(p) for p in pairs],
+           "gflops": out, "summary": summary,
+           "mask": "the first `cus` bits of the compute-unit mask"}
+    with open(os.path.join(out_dir, "cu_scaling_report.json"), "w") as f:
+        json.dump(rep, f, indent=1)
+    return rep
+
+
 # -------------------------------------------------------------------- MLP
 
 NP = 8769
@@ -552,7 +626,8 @@ def _lib_set_model(params, nmodels, fmean, fstd, ymean, ystd, cand):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["batched", "batched-tune", "sweep", "tune", "step1-cold", "ship",
+    ap.add_argument("what", choices=["batched", "batched-tune", "sweep", "tune", "step1-cold",
+                                     "cu-scaling", "ship",
                                      "collect-train",
                                      "collect-heldout", "mlp"])
     ap.add_argument("--out", required=True)
@@ -576,6 +651,8 @@ def main(argv=None):
         tune(a.out, db)
     elif a.what == "step1-cold":
         step1_cold(a.out, db)
+    elif a.what == "cu-scaling":
+        cu_scaling(a.out)
     elif a.what in ("collect-train", "collect-heldout"):
         done = collect(db, a.what.split("-")[1], a.budget)
         log("collect %s: %s" % (a.what, "complete" if done else "budget reached"))
