@@ -72,7 +72,8 @@ int64_t qr_T_size(int64_t M, int64_t N, int NB, int IB);
  *  NB  tile order, 16 <= NB <= 512; IB inner block, 1 <= IB <= NB (IB need
  *      not divide NB: the last block of a tile is narrower). NB = 0 or IB = 0:
  *      taken from qr_tune(M, N, 1). The tile classes above
- *      NB = 128 are currently switched off (TILEQR_ERR_DISABLED).
+ *      NB = 128 are currently switched off (TILEQR_ERR_DISABLED). The
+ *      persistent grid is sized for qr_tune_units(M, N, 1) compute units.
  *  T   (out, device, qr_T_size(M, N, NB, IB) doubles): the T factors.
  * One persistent kernel runs the whole DAG; the dependency counters and the
  * task order are library state, so calls on the same device must not
@@ -111,11 +112,12 @@ int qr_factor_loop(double *const *A, const int64_t *M, const int64_t *N, const i
                    int64_t count, const int *NB, const int *IB, double *const *T, void *stream);
 
 /* Sizes the persistent grid, and the schedule the host builds for it, for
- * `cus` compute units (0 or the device's count: all of them) in the launches
- * that follow: the setting for a stream created with a compute-unit mask
- * (hipExtStreamCreateWithCUMask) of that many units, the analog of the core
- * count of Sections 4-6. Errors: -1 cus < 0 or above the device's count;
- * positive: no device. */
+ * `cus` compute units in the launches that follow (the device's count: all
+ * of them; 0: no setting, the decision table's units decide, see
+ * qr_tune_units): the setting for a stream created with a compute-unit mask
+ * (hipExtStreamCreateWithCUMask) of that many units, or a smaller grid on
+ * the whole device; the analog of the core count of Sections 4-6. Errors:
+ * -1 cus < 0 or above the device's count; positive: no device. */
 int qr_set_compute_units(int cus);
 
 /* Waits for the stream, then returns (and clears) the first error the device
@@ -182,9 +184,18 @@ int qr_ssrfb_bench_flush(int NB, int IB, int calls, int workers, int64_t flush_b
  * Errors: -1 M < 0, -2 N < 0, -3 batch < 1, -4 NB null, -5 IB null. */
 int qr_tune(int64_t M, int64_t N, int64_t batch, int *NB, int *IB, int *source);
 
+/* Host only. The compute units the persistent grid of an M x N
+ * factorization is sized for: the qr_set_compute_units setting if one is
+ * made, else the decision table's nearest entry's units (0: all units).
+ * qr_factor and qr_apply_Qt use this value. Errors: -1 M, -2 N, -3 batch,
+ * -4 cus null. */
+int qr_tune_units(int64_t M, int64_t N, int64_t batch, int *cus);
+
 /* Loads a decision table (host path; text: lines "entry M N batch NB IB
- * gflops", optional "default NB IB", '#' comments), replacing the current
- * one. Returns 0, TILEQR_ERR_NOTABLE, or -1 for a null path. */
+ * gflops [units]", where units is the compute-unit count the grid is sized
+ * for, 0 or absent for all; optional "default NB IB"; '#' comments),
+ * replacing the current one. Returns 0, TILEQR_ERR_NOTABLE, or -1 for a
+ * null path. */
 int qr_tune_load(const char *path);
 
 /* Installs (or with nmodels = 0 removes) the ensemble of cost models used by

@@ -15,7 +15,7 @@ from ._lib import TileQRError, check
 
 __all__ = [
     "colmajor", "T_size", "factor", "apply_Qt", "factor_batched", "factor_loop", "set_compute_units", "sync",
-    "tile_task", "ssrfb_bench", "ssrfb_bench_flush", "tune", "tune_load", "flops", "flops_executed", "dag_counts",
+    "tile_task", "ssrfb_bench", "ssrfb_bench_flush", "tune", "tune_units", "tune_load", "flops", "flops_executed", "dag_counts",
     "plan_check", "plan_tasks", "TileQRError", "check",
 ]
 
@@ -77,6 +77,14 @@ def tune(M, N, batch=1):
     nb, ib, src = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     check(_lib.lib().qr_tune(M, N, batch, ctypes.byref(nb), ctypes.byref(ib), ctypes.byref(src)), "qr_tune")
     return nb.value, ib.value, src.value
+
+
+def tune_units(M, N, batch=1):
+    """Compute units the grid of an M x N factorization is sized for (0: all)."""
+    _ensure_table()
+    cus = ctypes.c_int()
+    check(_lib.lib().qr_tune_units(M, N, batch, ctypes.byref(cus)), "qr_tune_units")
+    return cus.value
 
 
 def tune_load(path):

@@ -275,6 +275,8 @@ int resolve_tiling(int64_t M, int64_t N, int64_t batch, int *nb, int *ib) {
   return 0;
 }
 
+int units_for(int64_t M, int64_t N, int64_t batch);
+
 int factor_one(double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, double *T,
                hipStream_t st, const DevState &ds) {
   if (M == 0 || N == 0) return 0;
@@ -283,6 +285,7 @@ int factor_one(double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, dou
   md_setup(md, M, N, NB, IB, mbt_for_nb(NB), 0);
   md.lda = lda;
   PlanKey key{0, 0, NB, IB, M, N, 0, 0};
+  key.cus = units_for(M, N, 1);
   hipGetDevice(&key.dev);
   Plan *p = nullptr;
   int rc = get_plan(key, {md}, false, ds, &p);
@@ -313,9 +316,40 @@ struct TableEntry {
   int64_t M, N, batch;
   int nb, ib;
   double gflops;
+  int cus;  // compute units the grid is sized for (0: all)
 };
 std::vector<TableEntry> g_table;
 int g_default_nb = 128, g_default_ib = 32;
+
+// Nearest benchmarked configuration (Section 6.1): log M, log N, log batch;
+// ties go to the larger configuration. nullptr when the table is empty.
+const TableEntry *nearest_entry(int64_t M, int64_t N, int64_t batch) {
+  const double lm = std::log((double)std::max<int64_t>(M, 1)),
+               ln = std::log((double)std::max<int64_t>(N, 1)), lb = std::log((double)batch);
+  const TableEntry *best = nullptr;
+  double bd = 1e300;
+  int64_t bsize = -1;
+  for (const TableEntry &e : g_table) {
+    const double d = std::pow(std::log((double)e.M) - lm, 2) +
+                     std::pow(std::log((double)e.N) - ln, 2) +
+                     std::pow(std::log((double)e.batch) - lb, 2);
+    const int64_t size = e.M * e.N * e.batch;
+    if (d < bd - 1e-12 || (std::fabs(d - bd) <= 1e-12 && size > bsize)) {
+      bd = d;
+      bsize = size;
+      best = &e;
+    }
+  }
+  return best;
+}
+
+// Units for one factorization: the explicit setting if any, else the
+// decision table's choice for the shape (0: all).
+int units_for(int64_t M, int64_t N, int64_t batch) {
+  if (g_cu_limit > 0) return g_cu_limit;
+  const TableEntry *e = nearest_entry(M, N, batch);
+  return e ? e->cus : 0;
+}
 
 struct ModelState {
   int nmodels = 0;
@@ -395,6 +429,7 @@ int qr_apply_Qt(const double *A, int64_t M, int64_t N, int64_t lda, int NB, int 
   md.lda = lda;
   md.ldb = ldb;
   PlanKey key{0, 1, NB, IB, M, N, nrhs, 0};
+  key.cus = units_for(M, N, 1);
   hipGetDevice(&key.dev);
   Plan *p = nullptr;
   if ((rc = get_plan(key, {md}, true, *ds, &p))) return rc;
@@ -524,7 +559,7 @@ int qr_set_compute_units(int cus) {
   int rc = dev_state(&ds);
   if (rc) return rc;
   if (cus > ds->ncu) return -1;
-  g_cu_limit = cus == ds->ncu ? 0 : cus;
+  g_cu_limit = cus;
   return 0;
 }
 
@@ -737,8 +772,11 @@ int qr_tune_load(const char *path) {
     if (*p == '#' || *p == '\n' || *p == 0) continue;
     TableEntry e;
     long long m, n, b;
-    if (std::sscanf(p, "entry %lld %lld %lld %d %d %lf", &m, &n, &b, &e.nb, &e.ib, &e.gflops) ==
-        6) {
+    e.cus = 0;
+    const int got = std::sscanf(p, "entry %lld %lld %lld %d %d %lf %d", &m, &n, &b, &e.nb, &e.ib,
+                                &e.gflops, &e.cus);
+    if (got == 6 || got == 7) {
+      if (e.cus < 0) bad = true;
       e.M = m;
       e.N = n;
       e.batch = b;
@@ -806,24 +844,9 @@ int qr_tune(int64_t M, int64_t N, int64_t batch, int *NB, int *IB, int *source) 
   }
   std::lock_guard<std::mutex> lk(g_mu);
   int nb = g_default_nb, ib = g_default_ib;
-  if (!g_table.empty()) {
-    // Nearest benchmarked configuration in (log M, log N, log batch); ties
-    // go to the larger configuration.
-    double lm = std::log((double)std::max<int64_t>(M, 1)), ln = std::log((double)std::max<int64_t>(N, 1)),
-           lb = std::log((double)batch);
-    double best = 1e300;
-    int64_t bestsize = -1;
-    for (const TableEntry &e : g_table) {
-      double d = std::pow(std::log((double)e.M) - lm, 2) + std::pow(std::log((double)e.N) - ln, 2) +
-                 std::pow(std::log((double)e.batch) - lb, 2);
-      int64_t size = e.M * e.N * e.batch;
-      if (d < best - 1e-12 || (std::fabs(d - best) <= 1e-12 && size > bestsize)) {
-        best = d;
-        bestsize = size;
-        nb = e.nb;
-        ib = e.ib;
-      }
-    }
+  if (const TableEntry *e = nearest_entry(M, N, batch)) {
+    nb = e->nb;
+    ib = e->ib;
     src = 1;
   }
   if (g_model.nmodels > 0) {
@@ -845,6 +868,16 @@ int qr_tune(int64_t M, int64_t N, int64_t batch, int *NB, int *IB, int *source) 
   *NB = nb;
   *IB = std::min(ib, nb);
   if (source) *source = src;
+  return 0;
+}
+
+int qr_tune_units(int64_t M, int64_t N, int64_t batch, int *cus) {
+  if (M < 0) return -1;
+  if (N < 0) return -2;
+  if (batch < 1) return -3;
+  if (!cus) return -4;
+  std::lock_guard<std::mutex> lk(g_mu);
+  *cus = units_for(M, N, batch);
   return 0;
 }
 

@@ -243,36 +243,41 @@ def tune(out_dir, db):
     return rep
 
 
-def ship_table(tune_dir, out_path, heuristic="2r", batch_count=2000):
-    """The decision table the library ships: the Step-2 (PSPAYG) decisions
-    of `heuristic` for single matrices plus the per-size-class decisions of
-    the batched tuning (entries with the batch count)."""
-    src = os.path.join(tune_dir, "decision_table_h%s_pspayg.txt" % heuristic)
+def ship_table(tune_dir, out_path, heuristic="2r", batch_count=2000, src_name=None):
+    """The decision table the library ships: the Step-2 decisions for single
+    matrices (`src_name` in tune_dir, by default heuristic's PSPAYG table;
+    entries may carry a unit count) plus the per-size-class decisions of the
+    batched tuning (entries with the batch count)."""
+    src = os.path.join(tune_dir, src_name or "decision_table_h%s_pspayg.txt" % heuristic)
     entries = []
     default = (128, 16)
     with open(src) as f:
         for line in f:
             w = line.split()
             if w and w[0] == "entry":
-                entries.append(tuple(int(x) for x in w[1:6]) + (float(w[6]),))
+                entries.append(tuple(int(x) for x in w[1:6]) + (float(w[6]),) +
+                               ((int(w[7]),) if len(w) > 7 else (0,)))
     bt = os.path.join(tune_dir, "batched_tune.json")
     if os.path.exists(bt):
         with open(bt) as f:
             for k, (nb, ib, g) in json.load(f).items():
                 m, n = (int(x) for x in k.split("x"))
-                entries.append((m, n, batch_count, nb, ib, g))
+                entries.append((m, n, batch_count, nb, ib, g, 0))
     big = max((e for e in entries if e[2] == 1), key=lambda e: e[0] * e[1], default=None)
     if big is not None:
         default = (big[3], big[4])
     with open(out_path, "w") as f:
         f.write("# tileqr decision table: entry M N batch NB IB gflops\n")
-        f.write("# single matrices: Step 2 with pruning as you go over the pairs of heuristic %s;\n"
-                % heuristic)
+        f.write("# single matrices: Step 2 over the pairs of heuristic %s (%s);\n"
+                % (heuristic, os.path.basename(src)))
         f.write("# batch %d: per size class (M, N rounded up to powers of two; the entry holds\n"
                 "# the class's geometric-mean shape)\n" % batch_count)
         f.write("default %d %d\n" % default)
         for e in sorted(entries, key=lambda e: (e[2], e[0], e[1])):
-            f.write("entry %d %d %d %d %d %.3f\n" % e)
+            if e[6]:
+                f.write("entry %d %d %d %d %d %.3f %d\n" % e)
+            else:
+                f.write("entry %d %d %d %d %d %.3f\n" % e[:6])
     return entries
 
 
@@ -373,6 +378,53 @@ def cu_scaling(out_dir, sizes=(4096, 8192, 16384), cus_list=(32, 64, 128, 256),
            "gflops": out, "summary": summary,
            "mask": "the first `cus` bits of the compute-unit mask"}
     with open(os.path.join(out_dir, "cu_scaling_report.json"), "w") as f:
+        json.dump(rep, f, indent=1)
+    return rep
+
+
+def tune_units(out_dir, db, units_list=(64, 128, 0)):
+    """Step 2 with the compute-unit count as a third tunable: every
+    pre-selected pair of the shipped heuristic at each unit count (0: all)
+    on the size grid; the best (NB, IB, units) per grid shape makes the
+    table, which is then scored on the test shapes against the exhaustive
+    search over the pairs on the whole device."""
+    import paper_1102_5328_amd as tq
+    ps = shipped_preselection()
+    meas = R.Measurer(db)
+    dec, t = {}, 0.0
+    for (M, N) in R.STEP2_GRID:
+        best = None
+        for nb, ib in ps:
+            for u in units_list:
+                g, sec = meas.measure(M, N, nb, ib, units=u)
+                t += sec
+                if best is None or g > best[2]:
+                    best = (nb, ib, g, u)
+        dec[(M, N)] = best
+        meas.save()
+        log("grid %dx%d: best NB=%d IB=%d units=%s %.1f GFLOP/s" %
+            (M, N, best[0], best[1], best[3] or "all", best[2]))
+    path = os.path.join(out_dir, "decision_table_h2r_units.txt")
+    S2.write_table(path, dec, comment="heuristic 2r pairs x compute units %s (0: all)" %
+                   (list(units_list),))
+    tq.tune_load(path)
+    rows = []
+    for kind, M, N in R.TEST_SHAPES:
+        nb, ib, _ = tq.tune(M, N, 1)
+        u = tq.tune_units(M, N, 1)
+        g = meas.measure(M, N, nb, ib, kind=kind, units=u)[0]
+        es = max(meas.db[R.Measurer.key(kind, M, N, p[0], p[1])]["gflops"]
+                 for p in R.config2_pairs())
+        rows.append({"kind": kind, "M": M, "N": N, "nb": nb, "ib": ib, "units": u,
+                     "gflops": g, "es_pairs_gflops": es, "pct_of_es_pairs": S2.percent(g, es)})
+        log("test %s %dx%d: NB=%d IB=%d units=%s %.1f GFLOP/s = %.1f%% of the pairs-only ES" %
+            (kind, M, N, nb, ib, u or "all", g, 100.0 * g / es))
+    meas.save()
+    rep = {"units": list(units_list), "preselected": [list(p) for p in ps],
+           "step2_seconds": t, "grid": {"%dx%d" % k: list(v) for k, v in dec.items()},
+           "test": rows, "avg_pct_of_es_pairs": round(float(np.mean([r["pct_of_es_pairs"]
+                                                                    for r in rows])), 2)}
+    with open(os.path.join(out_dir, "tune_units_report.json"), "w") as f:
         json.dump(rep, f, indent=1)
     return rep
 
@@ -627,16 +679,17 @@ def _lib_set_model(params, nmodels, fmean, fstd, ymean, ystd, cand):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("what", choices=["batched", "batched-tune", "sweep", "tune", "step1-cold",
-                                     "cu-scaling", "ship",
+                                     "cu-scaling", "tune-units", "ship",
                                      "collect-train",
                                      "collect-heldout", "mlp"])
     ap.add_argument("--out", required=True)
     ap.add_argument("--db", default=None, help="JSON measurement database (read and extended)")
     ap.add_argument("--budget", type=float, default=600.0, help="seconds of measuring (collect)")
+    ap.add_argument("--src", default=None, help="ship: the single-matrix decision table in --out")
     a = ap.parse_args(argv)
     os.makedirs(a.out, exist_ok=True)
     if a.what == "ship":
-        ship_table(a.out, os.path.join(TUNING, "decision_table.txt"))
+        ship_table(a.out, os.path.join(TUNING, "decision_table.txt"), src_name=a.src)
         return 0
     import torch
     torch.cuda.set_device(0)
@@ -653,6 +706,8 @@ def main(argv=None):
         step1_cold(a.out, db)
     elif a.what == "cu-scaling":
         cu_scaling(a.out)
+    elif a.what == "tune-units":
+        tune_units(a.out, db)
     elif a.what in ("collect-train", "collect-heldout"):
         done = collect(db, a.what.split("-")[1], a.budget)
         log("collect %s: %s" % (a.what, "complete" if done else "budget reached"))

@@ -56,8 +56,9 @@ class Measurer:
             os.replace(tmp, self.db_path)
 
     @staticmethod
-    def key(kind, M, N, nb, ib, batch=1):
-        return "%s:%d:%d:%d:%d:%d" % (kind, M, N, nb, ib, batch)
+    def key(kind, M, N, nb, ib, batch=1, units=0):
+        k = "%s:%d:%d:%d:%d:%d" % (kind, M, N, nb, ib, batch)
+        return k + (":u%d" % units if units else "")
 
     def _input(self, kind, M, N):
         import torch
@@ -74,9 +75,10 @@ class Measurer:
             self._shape = (kind, M, N)
         return self._A0
 
-    def measure(self, M, N, nb, ib, kind="normal", reps=None):
-        """(median GFLOP/s, seconds spent) for one configuration."""
-        k = self.key(kind, M, N, nb, ib)
+    def measure(self, M, N, nb, ib, kind="normal", reps=None, units=0):
+        """(median GFLOP/s, seconds spent) for one configuration; units > 0
+        sizes the persistent grid for that many compute units, 0 for all."""
+        k = self.key(kind, M, N, nb, ib, units=units)
         if k in self.db:
             r = self.db[k]
             return r["gflops"], r["seconds"]
@@ -89,6 +91,8 @@ class Measurer:
         A = tq.colmajor(M, N)
         T = torch.empty(max(1, tq.T_size(M, N, nb, ib)), dtype=torch.float64, device="cuda")
         fl = tq.flops(M, N)
+        import torch as _t
+        tq.set_compute_units(units if units else _t.cuda.get_device_properties(0).multi_processor_count)
         t_start = time.perf_counter()
         A.copy_(A0)
         tq.factor(A, nb, ib, T)
@@ -103,9 +107,10 @@ class Measurer:
             tq.sync()
             g.append(fl / (e0.elapsed_time(e1) * 1e-3) / 1e9)
         sec = time.perf_counter() - t_start
+        tq.set_compute_units(0)
         med = S2.median(g)
         self.db[k] = {"gflops": med, "max": max(g), "runs": g, "seconds": sec, "M": M, "N": N,
-                      "nb": nb, "ib": ib, "batch": 1, "kind": kind}
+                      "nb": nb, "ib": ib, "batch": 1, "kind": kind, "units": units}
         if self.verbose:
             print("measured %s %dx%d nb=%d ib=%d: %.1f GFLOP/s (%.2f s)" % (kind, M, N, nb, ib, med, sec),
                   flush=True)

@@ -83,8 +83,13 @@ def write_table(path, dec, batch=1, default=(128, 32), comment=None):
             for line in comment.splitlines():
                 f.write("# %s\n" % line)
         f.write("default %d %d\n" % default)
-        for (M, N), (nb, ib, g) in sorted(dec.items()):
-            f.write("entry %d %d %d %d %d %.3f\n" % (M, N, batch, nb, ib, g))
+        for (M, N), d in sorted(dec.items()):
+            nb, ib, g = d[:3]
+            units = d[3] if len(d) > 3 else 0
+            if units:
+                f.write("entry %d %d %d %d %d %.3f %d\n" % (M, N, batch, nb, ib, g, units))
+            else:
+                f.write("entry %d %d %d %d %d %.3f\n" % (M, N, batch, nb, ib, g))
 
 
 def median(xs):

@@ -280,3 +280,23 @@ def test_tune_set_model_argument_errors(lib):
     assert f(P(p), 1, P(fm), P(fs), 0.0, 1.0, bad.ctypes.data_as(I), 2) == -7
     assert f(P(p), 1, P(fm), P(fs), 0.0, 1.0, None, 2) == -7
     assert f(None, 0, None, None, 0.0, 1.0, None, 0) == 0
+
+
+def test_tune_units_from_table(lib, tmp_path, monkeypatch):
+    """The optional units column: the nearest entry's unit count sizes the
+    grid (0 or absent: all units); qr_set_compute_units is not needed."""
+    p = tmp_path / "units.txt"
+    p.write_text("default 128 16\nentry 4096 4096 1 64 16 2300.0 64\n"
+                 "entry 16384 16384 1 128 16 9200.0 0\nentry 2048 2048 1 64 16 450.0\n")
+    tq.tune_load(str(p))
+    try:
+        assert tq.tune_units(4000, 4200, 1) == 64
+        assert tq.tune_units(16000, 16000, 1) == 0
+        assert tq.tune_units(2000, 2000, 1) == 0
+        assert tq.tune(4000, 4200, 1) == (64, 16, 1)
+        assert lib.qr_tune_units(-1, 4, 1, ctypes.byref(ctypes.c_int())) == -1
+        assert lib.qr_tune_units(4, 4, 1, None) == -4
+        p.write_text("entry 4096 4096 1 64 16 2300.0 -3\n")
+        assert lib.qr_tune_load(str(p).encode()) == 7
+    finally:
+        tq.tune_load(os.devnull)
