@@ -267,7 +267,7 @@ def ship_table(tune_dir, out_path, heuristic="2r", batch_count=2000, src_name=No
     if big is not None:
         default = (big[3], big[4])
     with open(out_path, "w") as f:
-        f.write("# tileqr decision table: entry M N batch NB IB gflops\n")
+        f.write("# tileqr decision table: entry M N batch NB IB gflops [units; absent: all]\n")
         f.write("# single matrices: Step 2 over the pairs of heuristic %s (%s);\n"
                 % (heuristic, os.path.basename(src)))
         f.write("# batch %d: per size class (M, N rounded up to powers of two; the entry holds\n"
