@@ -686,6 +686,8 @@ def main(argv=None):
     ap.add_argument("--db", default=None, help="JSON measurement database (read and extended)")
     ap.add_argument("--budget", type=float, default=600.0, help="seconds of measuring (collect)")
     ap.add_argument("--src", default=None, help="ship: the single-matrix decision table in --out")
+    ap.add_argument("--units", default="64,128,0",
+                    help="tune-units: compute-unit counts to try (0: all)")
     a = ap.parse_args(argv)
     os.makedirs(a.out, exist_ok=True)
     if a.what == "ship":
@@ -707,7 +709,7 @@ def main(argv=None):
     elif a.what == "cu-scaling":
         cu_scaling(a.out)
     elif a.what == "tune-units":
-        tune_units(a.out, db)
+        tune_units(a.out, db, tuple(int(x) for x in a.units.split(",")))
     elif a.what in ("collect-train", "collect-heldout"):
         done = collect(db, a.what.split("-")[1], a.budget)
         log("collect %s: %s" % (a.what, "complete" if done else "budget reached"))
