@@ -185,7 +185,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "tile Householder QR of one %dx%d FP64 N(0,1) matrix" % (N, N),
-                   "M": N, "N": N, "NB": nb, "IB": ib, "tiling_source": src},
+                   "M": N, "N": N, "NB": nb, "IB": ib, "tiling_source": src,
+                   "compute_units": tq.tune_units(N, N, 1) or "all"},
         "pct_fp64_peak": round(100.0 * value / (PEAK_FP64_TFLOPS * 1e3), 2),
         "tuned_vs_exhaustive_pct": tuned_vs_exhaustive(N, nb, ib),
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3),

@@ -17,7 +17,8 @@
  *    the comment says host. The caller allocates and owns every buffer; the
  *    library never frees caller memory. The library keeps only internal
  *    state (cached task lists, dependency counters, captured graphs, the
- *    decision table), released at process exit.
+ *    decision table, the cost model, the compute-unit setting), process-wide
+ *    and released at process exit.
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *    Device work is enqueued asynchronously on it; the return code covers
  *    argument checking and launch errors. qr_sync() reports errors found by
