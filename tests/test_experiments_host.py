@@ -61,3 +61,16 @@ def test_ship_table(tmp_path, monkeypatch):
     lines = [l for l in out.read_text().splitlines() if not l.startswith("#")]
     assert lines[0] == "default 128 16"  # the decision at the largest benchmarked size
     assert "entry 85 47 2000 128 16 58.700" in lines
+
+
+def test_ship_table_carries_units(tmp_path):
+    d = tmp_path / "run"
+    d.mkdir()
+    (d / "decision_table_h2r_units.txt").write_text(
+        "default 128 16\nentry 4096 4096 1 64 16 2300.0 64\nentry 16384 16384 1 128 16 9200.0\n")
+    out = tmp_path / "table.txt"
+    E.ship_table(str(d), str(out), src_name="decision_table_h2r_units.txt")
+    lines = [l for l in out.read_text().splitlines() if not l.startswith("#")]
+    assert "entry 4096 4096 1 64 16 2300.000 64" in lines
+    assert "entry 16384 16384 1 128 16 9200.000" in lines
+    assert lines[0] == "default 128 16"
