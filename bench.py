@@ -33,7 +33,7 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(N, nb, ib):
+def measured_traffic(N, nb, ib, units):
     """HBM bytes per launch of the persistent kernel from the rocprofv3
     counter runs recorded in profiles/traffic.txt (FETCH_SIZE and WRITE_SIZE,
     each scaled by the same counter's reading for a device copy of known
@@ -47,7 +47,7 @@ def measured_traffic(N, nb, ib):
             w = dict(x.split("=", 1) for x in line.split() if "=" in x)
             if (w.get("kernel") == "tq_persistent" and w.get("src") == h and
                     int(w.get("N", -1)) == N and int(w.get("NB", -1)) == nb and
-                    int(w.get("IB", -1)) == ib):
+                    int(w.get("IB", -1)) == ib and int(w.get("units", 0)) == units):
                 return float(w["bytes"])
     return None
 
@@ -166,7 +166,8 @@ def main():
     dt = time.perf_counter() - t0
     tq.sync()
     kern_ms = sum(e0.elapsed_time(e1) for e0, e1 in evs) / args.steps
-    traffic = measured_traffic(N, nb, ib)
+    units = tq.tune_units(N, N, 1)
+    traffic = measured_traffic(N, nb, ib, units)
     ms_per_step = dt * 1e3 / args.steps
     flops = tq.flops(N, N)
     value = flops / (ms_per_step * 1e-3) / 1e9
@@ -186,7 +187,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "tile Householder QR of one %dx%d FP64 N(0,1) matrix" % (N, N),
                    "M": N, "N": N, "NB": nb, "IB": ib, "tiling_source": src,
-                   "compute_units": tq.tune_units(N, N, 1) or "all"},
+                   "compute_units": units or "all"},
         "pct_fp64_peak": round(100.0 * value / (PEAK_FP64_TFLOPS * 1e3), 2),
         "tuned_vs_exhaustive_pct": tuned_vs_exhaustive(N, nb, ib),
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3),
