@@ -84,18 +84,11 @@ static void apply_reflector(int64_t m, const double *v, int64_t ldv, int64_t j,
     }
 }
 
-/* Unblocked Householder QR: on exit R is in the upper triangle/trapezoid of
- * A, the reflectors' tails below the diagonal, tau[0..K-1] the scalars. */
-void oracle_geqr2(int64_t m, int64_t n, double *a, int64_t lda, double *tau) {
-    int64_t k = m < n ? m : n;
-    for (int64_t j = 0; j < k; ++j) {
-        tau[j] = make_reflector(m, a, lda, j);
-        apply_reflector(m, a, lda, j, tau[j], a, lda, j + 1, n);
-    }
-}
-
-/* The first `steps` Householder steps only (a bounded sample of the full
- * factorization, used to time the oracle on large inputs). */
+/* The first `steps` Householder steps of the unblocked QR (all K = min(m, n)
+ * of them when steps >= K): column j's reflector is generated, then applied
+ * to every column to its right. A bounded number of steps is the sample the
+ * benchmark times on large inputs; the full factorization below is the same
+ * loop run to the end, so both share one code path. */
 void oracle_geqr2_steps(int64_t m, int64_t n, double *a, int64_t lda,
                         double *tau, int64_t steps) {
     int64_t k = m < n ? m : n;
@@ -104,6 +97,12 @@ void oracle_geqr2_steps(int64_t m, int64_t n, double *a, int64_t lda,
         tau[j] = make_reflector(m, a, lda, j);
         apply_reflector(m, a, lda, j, tau[j], a, lda, j + 1, n);
     }
+}
+
+/* Unblocked Householder QR: on exit R is in the upper triangle/trapezoid of
+ * A, the reflectors' tails below the diagonal, tau[0..K-1] the scalars. */
+void oracle_geqr2(int64_t m, int64_t n, double *a, int64_t lda, double *tau) {
+    oracle_geqr2_steps(m, n, a, lda, tau, m < n ? m : n);
 }
 
 /* B <- Q^T B = H_{K-1} ... H_0 B: reflectors applied in ascending order. */

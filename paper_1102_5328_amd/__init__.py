@@ -97,6 +97,10 @@ def factor(A, nb=0, ib=0, T=None, stream=None):
     """In-place tile QR of the column-major FP64 tensor A. Returns (A, T, nb, ib)."""
     torch = _torch()
     M, N = A.shape
+    # The grid size of the launch comes from the decision table's units
+    # unless set_compute_units was called: load it first, so a call sizes its
+    # grid the same way whatever ran before it.
+    _ensure_table()
     if nb == 0 or ib == 0:
         tnb, tib, _ = tune(M, N, 1)
         nb = nb or tnb
@@ -111,6 +115,7 @@ def factor(A, nb=0, ib=0, T=None, stream=None):
 def apply_Qt(A, T, nb, ib, B, stream=None):
     """B <- Q^T B in place (B column-major, M rows)."""
     M, N = A.shape
+    _ensure_table()
     check(_lib.lib().qr_apply_Qt(ctypes.c_void_p(A.data_ptr()), M, N, _ld(A), nb, ib,
                                  ctypes.c_void_p(T.data_ptr()), ctypes.c_void_p(B.data_ptr()),
                                  B.shape[1], _ld(B), _stream(stream)), "qr_apply_Qt")
@@ -132,6 +137,7 @@ def _batch_args(As, nbs, ibs, Ts):
 
 def factor_batched(As, nbs, ibs, Ts, stream=None):
     """One persistent, graph-captured launch over all matrices."""
+    _ensure_table()
     a, m, n, ld, nb, ib, t = _batch_args(As, nbs, ibs, Ts)
     check(_lib.lib().qr_factor_batched(ctypes.cast(a, ctypes.c_void_p), m, n, ld, len(As), nb, ib,
                                        ctypes.cast(t, ctypes.c_void_p), _stream(stream)),
@@ -140,6 +146,7 @@ def factor_batched(As, nbs, ibs, Ts, stream=None):
 
 def factor_loop(As, nbs, ibs, Ts, stream=None):
     """One qr_factor launch per matrix (the baseline of the batched launch)."""
+    _ensure_table()
     a, m, n, ld, nb, ib, t = _batch_args(As, nbs, ibs, Ts)
     check(_lib.lib().qr_factor_loop(ctypes.cast(a, ctypes.c_void_p), m, n, ld, len(As), nb, ib,
                                     ctypes.cast(t, ctypes.c_void_p), _stream(stream)),

@@ -25,11 +25,14 @@ def _assert_ok(r):
         assert r["orth"] <= r["bound"], r
 
 
-def test_config1_512_nb128_ib32():
-    """Configuration 1: M = N = 512, NB = 128, IB = 32, uniform[-1,1], seed 0."""
+@pytest.mark.parametrize("units", [None, 16, 1])
+def test_config1_512_nb128_ib32(units):
+    """Configuration 1: M = N = 512, NB = 128, IB = 32, uniform[-1,1], seed 0,
+    on the full grid, on 16 compute units, and on a single one (two
+    workgroups take every task in ticket order)."""
     A = inputs.uniform(512, 512, seed=0)
-    r = check_factorization(A, 128, 32)
-    print("config1", r)
+    r = check_factorization(A, 128, 32, units=units)
+    print("config1", units, r)
     _assert_ok(r)
 
 

@@ -215,3 +215,60 @@ def test_mlp_forward_hand_computed(orc):
     X = np.array([[1.0, 0, 0, 0, 0], [-4.0, 0, 0, 0, 0]])
     # x=1: h1=3, h2=9, h3=relu(-9+10)=1, y=0.75 ; x=-4: h1=relu(-7)=0 -> h3=10, y=5.25
     np.testing.assert_allclose(orc.mlp_forward(p, X), [0.75, 5.25])
+
+
+@pytest.mark.parametrize("shape", [(40, 25), (25, 40), (33, 33)])
+def test_geqr2_steps_is_a_prefix_of_the_full_factorization(orc, shape):
+    """The benchmark's CPU baseline times oracle_geqr2_steps. After s steps
+    the first s columns (R rows and reflector tails) and tau[0:s] are final,
+    so they equal the full factorization's bit for bit; the trailing columns
+    hold H_{s-1} ... H_0 A[:, s:], i.e. Q_s^T applied to the original columns
+    (Q_s from the first s reflectors, applied one at a time by apply_qt);
+    s >= K is the full factorization."""
+    M, N = shape
+    K = min(M, N)
+    A = inputs.normal(M, N, seed=31)
+    VR, tau = orc.geqr2(A)
+    for s in [0, 1, 2, 7, K - 1, K, K + 3]:
+        a = np.asfortranarray(A.copy())
+        ts = orc.geqr2_steps_inplace(a, s)
+        sk = min(s, K)
+        np.testing.assert_array_equal(a[:, :sk], VR[:, :sk])
+        np.testing.assert_array_equal(ts[:sk], tau[:sk])
+        if sk < N:
+            trail = orc.apply_qt(VR[:, :sk], tau[:sk], A[:, sk:])
+            np.testing.assert_allclose(a[:, sk:], trail, rtol=0, atol=1e-13)
+        if s >= K:
+            np.testing.assert_array_equal(a, VR)
+
+
+def test_mlp_forward_hand_computed_negative_preactivations(orc):
+    """Pre-activations go negative in every hidden layer, so dropping any
+    ReLU changes the output (values worked by hand):
+      h1 = relu(x0);  z2 = (h1 - 2, 1 - h1);  z3 = (h2_0 + h2_1 - 1/4, 1 - 3 h2_0);
+      y = h3_0 + 2 h3_1.
+    x0 = 3:   h1 = 3, z2 = (1, -2),  h2 = (1, 0),   z3 = (3/4, -2),  y = 3/4
+    x0 = 1/2: h1 = 1/2, z2 = (-3/2, 1/2), h2 = (0, 1/2), z3 = (1/4, 1), y = 9/4
+    x0 = -1:  z1 = -1 -> h1 = 0, z2 = (-2, 1), h2 = (0, 1), z3 = (3/4, 1), y = 11/4
+    Without the layer-2 ReLU the first row gives 0; without the layer-3 ReLU
+    it gives -13/4; without the layer-1 ReLU the third row gives 3/4."""
+    p = np.zeros(orc.MLP_NPARAM)
+    W1, b1, W2, b2, W3, b3, W4, b4 = 0, 320, 384, 4480, 4544, 8640, 8704, 8768
+    p[W1 + 0 * 5 + 0] = 1.0
+    p[W2 + 0 * 64 + 0], p[b2 + 0] = 1.0, -2.0
+    p[W2 + 1 * 64 + 0], p[b2 + 1] = -1.0, 1.0
+    p[W3 + 0 * 64 + 0], p[W3 + 0 * 64 + 1], p[b3 + 0] = 1.0, 1.0, -0.25
+    p[W3 + 1 * 64 + 0], p[b3 + 1] = -3.0, 1.0
+    p[W4 + 0], p[W4 + 1], p[b4] = 1.0, 2.0, 0.0
+    X = np.zeros((3, 5))
+    X[:, 0] = [3.0, 0.5, -1.0]
+    np.testing.assert_allclose(orc.mlp_forward(p, X), [0.75, 2.25, 2.75], rtol=0, atol=1e-15)
+    # The analytic gradient at this point: with targets 0, dL/db4 = mean(yhat)
+    # and dL/dW4[1] = mean(yhat * h3_1) (h3_1 = 0, 1, 1 on the three rows).
+    loss, g = orc.mlp_grad(p, X, np.zeros(3))
+    assert loss == pytest.approx((0.75 ** 2 + 2.25 ** 2 + 2.75 ** 2) / 6, rel=1e-15)
+    assert g[b4] == pytest.approx((0.75 + 2.25 + 2.75) / 3, rel=1e-15)
+    assert g[W4 + 1] == pytest.approx((2.25 + 2.75) / 3, rel=1e-15)
+    # Row 1 (x0 = 3) has z3_1 < 0, so W3[1][0] gets its gradient from rows
+    # 2 and 3 only, where h2_0 = 0: zero in all.
+    assert g[W3 + 1 * 64 + 0] == 0.0
