@@ -23,11 +23,10 @@ struct TqLaunch {
   long long timeout;    // wall-clock ticks
   size_t lds_bytes;
   int grid;
-  int mbt;
   long long *trace;     // optional: 4 wall-clock stamps per task, or nullptr
 };
 
 hipError_t tq_launch_persistent(const TqLaunch &a, hipStream_t st);
-int tq_occupancy(int mbt, size_t lds_bytes);
+int tq_occupancy(size_t lds_bytes);
 hipError_t tq_launch_ssrfb_bench(double *buf, int nb, int ib, int calls, int grid, hipStream_t st);
 hipError_t tq_launch_fill(double *p, int64_t n, uint64_t seed, double scale, hipStream_t st);

@@ -76,7 +76,6 @@ struct Plan {
   MatDesc *d_mats = nullptr;
   std::vector<MatDesc> mats;  // host copy (pointers filled per call for singles)
   int grid = 1;
-  int mbt = 4;
   size_t lds = 0;
   hipGraphExec_t graph = nullptr;
   ~Plan() {
@@ -122,10 +121,10 @@ void touch(const PlanKey &k) {
   }
 }
 
-// Geometry of one matrix for a kernel class: strip width and staged chunks.
-void md_setup(MatDesc &md, int64_t M, int64_t N, int nb, int ib, int mbt, int64_t nrhs) {
-  const LdsPlan lp = lds_plan(mbt, ib);
-  md_init(md, M, N, nb, ib, 16 * lp.nw, nrhs);
+// Geometry of one matrix: strip width and staged V chunks.
+void md_setup(MatDesc &md, int64_t M, int64_t N, int nb, int ib, int64_t nrhs) {
+  const LdsPlan lp = lds_plan(nb, ib);
+  md_init(md, M, N, nb, ib, strip_width(nb), nrhs);
   md.gmax = lp.gmax;
 }
 
@@ -138,20 +137,17 @@ int get_plan(const PlanKey &key, std::vector<MatDesc> mats, bool apply, const De
     *out = it->second;
     return 0;
   }
-  int mbt = 4;
-  for (const MatDesc &m : mats) mbt = std::max(mbt, mbt_for_nb(m.nb));
   size_t lds = 0;
   int64_t ctr = 0;
   for (MatDesc &m : mats) {
     m.ctr = ctr;
     ctr += apply ? ctr_count_apply(m) : ctr_count_factor(m);
-    lds = std::max(lds, (size_t)lds_plan(mbt, m.ib).doubles * 8);
+    lds = std::max(lds, (size_t)lds_plan(m.nb, m.ib).doubles * 8);
   }
-  int occ = tq_occupancy(mbt, lds);
+  int occ = tq_occupancy(lds);
   const int cus = (key.cus > 0 && key.cus < ds.ncu) ? key.cus : ds.ncu;
   int grid = std::max(1, cus * occ);
   Plan *p = new Plan();
-  p->mbt = mbt;
   p->lds = lds;
   std::vector<Task> order;
   int64_t nctr = 0;
@@ -227,7 +223,6 @@ TqLaunch make_launch(const Plan &p, const DevState &ds, const MatDesc &single) {
   a.timeout = watchdog_ticks(ds);
   a.lds_bytes = p.lds;
   a.grid = p.grid;
-  a.mbt = p.mbt;
   a.trace = nullptr;
   return a;
 }
@@ -282,7 +277,7 @@ int factor_one(double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, dou
   if (M == 0 || N == 0) return 0;
   MatDesc md;
   std::memset(&md, 0, sizeof(md));
-  md_setup(md, M, N, NB, IB, mbt_for_nb(NB), 0);
+  md_setup(md, M, N, NB, IB, 0);
   md.lda = lda;
   PlanKey key{0, 0, NB, IB, M, N, 0, 0};
   key.cus = units_for(M, N, 1);
@@ -424,7 +419,7 @@ int qr_apply_Qt(const double *A, int64_t M, int64_t N, int64_t lda, int NB, int 
   if ((rc = dev_state(&ds))) return rc;
   MatDesc md;
   std::memset(&md, 0, sizeof(md));
-  md_setup(md, M, N, NB, IB, mbt_for_nb(NB), nrhs);
+  md_setup(md, M, N, NB, IB, nrhs);
   if ((int64_t)md.SB > 4095) return TILEQR_ERR_TOO_LARGE;
   md.lda = lda;
   md.ldb = ldb;
@@ -488,15 +483,12 @@ int qr_factor_batched(double *const *A, const int64_t *M, const int64_t *N, cons
   DevState *ds;
   if ((rc = dev_state(&ds))) return rc;
   std::vector<MatDesc> mats;
-  int mbt = 4;
-  for (int64_t b = 0; b < count; ++b)
-    if (M[b] > 0 && N[b] > 0) mbt = std::max(mbt, mbt_for_nb(nbs[b]));
   uint64_t h = 1469598103934665603ull;
   for (int64_t b = 0; b < count; ++b) {
     if (M[b] == 0 || N[b] == 0) continue;
     MatDesc md;
     std::memset(&md, 0, sizeof(md));
-    md_setup(md, M[b], N[b], nbs[b], ibs[b], mbt, 0);
+    md_setup(md, M[b], N[b], nbs[b], ibs[b], 0);
     md.lda = lda[b];
     md.A = A[b];
     md.T = T[b];
@@ -593,7 +585,7 @@ int qr_tile_task(int kind, double *A, int64_t M, int64_t N, int64_t lda, int NB,
   if (!nb_enabled(NB)) return TILEQR_ERR_DISABLED;
   MatDesc md;
   std::memset(&md, 0, sizeof(md));
-  md_setup(md, M, N, NB, IB, mbt_for_nb(NB), 0);
+  md_setup(md, M, N, NB, IB, 0);
   md.lda = lda;
   md.A = A;
   md.T = T;
@@ -634,8 +626,7 @@ int qr_tile_task(int kind, double *A, int64_t M, int64_t N, int64_t lda, int NB,
   if (hipMemcpyAsync(d_tasks, tasks.data(), sizeof(Task) * tasks.size(), hipMemcpyHostToDevice,
                      st) != hipSuccess)
     rc = TILEQR_ERR_HIP;
-  int mbt = mbt_for_nb(NB);
-  size_t lds = (size_t)lds_plan(mbt, IB).doubles * 8;
+  size_t lds = (size_t)lds_plan(NB, IB).doubles * 8;
   TqLaunch a;
   a.tasks = d_tasks;
   a.ntasks = (int64_t)tasks.size();
@@ -650,7 +641,6 @@ int qr_tile_task(int kind, double *A, int64_t M, int64_t N, int64_t lda, int NB,
   a.timeout = watchdog_ticks(*ds);
   a.lds_bytes = lds;
   a.grid = (int)tasks.size();
-  a.mbt = mbt;
   a.trace = nullptr;
   if (!rc && tq_launch_persistent(a, st) != hipSuccess) rc = TILEQR_ERR_HIP;
   if (hipStreamSynchronize(st) != hipSuccess) rc = TILEQR_ERR_HIP;
@@ -967,7 +957,7 @@ int qr_plan_check(int64_t M, int64_t N, int NB, int IB, int64_t nrhs, int apply,
   if (M < 1 || N < 1 || !nb_ok(NB) || IB < 1 || IB > NB || workers < 1) return TILEQR_ERR_INTERNAL;
   MatDesc md;
   std::memset(&md, 0, sizeof(md));
-  md_setup(md, M, N, NB, IB, mbt_for_nb(NB), apply ? nrhs : 0);
+  md_setup(md, M, N, NB, IB, apply ? nrhs : 0);
   md.ctr = 0;
   std::vector<MatDesc> mats{md};
   std::vector<Task> order;
@@ -984,7 +974,7 @@ int qr_plan_tasks(int64_t M, int64_t N, int NB, int IB, int64_t nrhs, int apply,
   if (M < 1 || N < 1 || !nb_ok(NB) || IB < 1 || IB > NB || workers < 1) return TILEQR_ERR_INTERNAL;
   MatDesc md;
   std::memset(&md, 0, sizeof(md));
-  md_setup(md, M, N, NB, IB, mbt_for_nb(NB), apply ? nrhs : 0);
+  md_setup(md, M, N, NB, IB, apply ? nrhs : 0);
   md.ctr = 0;
   std::vector<MatDesc> mats{md};
   std::vector<Task> order;

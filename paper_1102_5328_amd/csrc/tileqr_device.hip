@@ -5,27 +5,35 @@
 // topological order, waits on the dependency counters of that task, runs it,
 // and bumps the counters of the data it wrote.
 //
+// Register layout: a wave holds a block of 128 rows x 16 columns in the
+// accumulator layout of v_mfma_f64_16x16x4f64 (lane l, item (t, r) holds row
+// 16t + 4r + l/16 of column l%16). Tiles taller than 128 rows are covered by
+// several waves ("row waves") that hold consecutive 128-row slabs of the
+// same 16 columns; see layout.h.
+//
 // Task bodies:
 //  * LARFB / SSRFB (and the updates inside the panels) apply a run of
 //    compact-WY block reflectors H = I - V T V^T, IB columns at a time:
 //        W = T^T (C1_s + V_s^T C2),  C1_s -= W,  C2 -= V_s W.
-//    Each wave owns a 16-column strip of C2 for the whole task, held in
-//    registers in the FP64 MFMA accumulator layout, so the contraction with
-//    V_s^T uses the accumulators directly as the B operand of
-//    v_mfma_f64_16x16x4 and the update accumulates into them. V is staged
-//    through LDS 16 columns at a time (coalesced loads, conflict-free
-//    transposed reads thanks to an odd leading dimension).
-//  * GEQRT / TSQRT factor IB-wide column blocks: up to 16 columns at a time
-//    are held in registers (rows spread over the 256 threads); each
-//    Householder column needs one reduction for its norm and one batched
-//    transpose-reduction for all its dot products, and builds the compact-WY
-//    factor T column by column from the same dot products. The rest of the
-//    tile is updated with the MFMA routine above.
+//    C2 stays in the wave registers for the whole task; its products with
+//    V_s^T and V_s run on the FP64 MFMA with the accumulators as operands.
+//    V_s and T_s are staged in LDS; when a block is small enough, the next
+//    block's V, T and C1 rows are loaded into registers while the current
+//    one computes, so each block costs two barriers and no exposed memory
+//    latency.
+//  * GEQRT / TSQRT factor a register panel of up to 64 columns held in
+//    registers by all four waves: per Householder column, one wave-level
+//    reduction for the norm, one LDS broadcast of the reflector, and one
+//    reduction for all the dot products (one barrier per column when the
+//    tile has at most 128 rows). The lanes of finished columns compute the
+//    Gram entries of the compact-WY factor T at no extra cost, and wave 0
+//    runs the T recurrence one column behind. The rest of the tile is then
+//    updated with the MFMA routine above.
 //
 // Storage: A column-major with leading dimension lda, tiles addressed in
 // place (ragged last tile row/column allowed). T of tile (i, k) is an
 // IB x nb_k array at T + (k*MT + i)*IB*NB, leading dimension IB; the block
-// of columns [s, s+IB) holds the upper-triangular T_s of those reflectors.
+// of columns [s, s+IB) holds the upper-triangular T_s (zero below).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -46,186 +54,256 @@ __device__ inline const gdbl *gp(const double *p) { return (const gdbl *)p; }
 namespace {
 
 constexpr int NTHR = TQ_NTHR;
-
-// Register classes up to this one are compiled for two waves per SIMD
-// (256 registers per lane); larger ones get the full register file.
-#ifndef TQ_WPE2_MAX_MBT
-#define TQ_WPE2_MAX_MBT 8
-#endif
+constexpr int RT = TQ_ROWS_PER_WAVE / 16;  // 16-row tiles per wave block
+constexpr int PF = 16;                     // doubles per lane of a register-staged V block
 enum { VK_UNIT = 0, VK_FULL = 1 };
 
-__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
-__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+// The thread index, opaque to the optimizer at every use: in a persistent
+// kernel every value derived from it (addresses, predicates of unrolled
+// loops) is loop-invariant, and hoisting all of them out of the task loop
+// would keep hundreds of them live for the whole kernel. The empty asm makes
+// the compiler recompute them where they are used instead.
+__device__ __forceinline__ int tid_x() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+__device__ __forceinline__ int lane_id() { return tid_x() & 63; }
+// Wave index in a scalar register (uniform across the wave).
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(tid_x() >> 6); }
 
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-struct Lds {
-  ldbl *vc;     // gmax chunks of 16 columns of V, column c at c * ldvc
-  ldbl *y;      // nw regions of ibp x 16 (Y, then W in place)
-  ldbl *ts;     // T_s of the current block, [a * ldts + c] (aliases the panel scratch)
-  ldbl *red1;   // 4
-  ldbl *red32;  // 4 x 16
-  ldbl *tot;    // 16 (+16)
-  ldbl *scal;   // 8
-  ldbl *tmm;    // 32 x 33 micro-panel T, [a*33 + c]
-  ldbl *top;    // 32 x 33 TSQRT top block
-  int ldvc, ibp, gmax;
+// Orders the wave's LDS accesses before this point against those after it
+// (the lanes of a wave run in lockstep; this pins the compiler's ordering).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sum over the four lanes that hold the rows of one column (l, l^16, l^32,
+// l^48); every one of them gets the total.
+__device__ inline double col_sum(double v) {
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
+
+// Geometry of a tile class with RW row waves per column group.
+template <int RW>
+struct Geo {
+  static constexpr int ROWS = TQ_ROWS_PER_WAVE * RW;  // rows of a staged V column
+  static constexpr int LDVC = ROWS + 1;               // odd: conflict-free transposed reads
+  static constexpr int CGN = 4 / RW;                  // column groups of 16
+  static constexpr int P = 16 * CGN;                  // strip / register panel width
 };
 
-__device__ inline Lds make_lds(double *lds_base, int mbt, int ib, int nw, int gmax) {
+struct Lds {
+  // update phase
+  ldbl *vc;  // gmax chunks of 16 columns of V, column c at c * ldvc
+  ldbl *y;   // one ibp x 16 region per column group (Y, then W in place)
+  ldbl *ts;  // T_s of the current block, [a * (ibp + 1) + c]
+  // panel phase (aliases the update phase)
+  ldbl *vb;    // 2 x rows: reflector broadcast, double-buffered
+  ldbl *taus;  // 64
+  ldbl *red;   // 4 x 2: norm and alpha partials of the row waves
+  ldbl *dred;  // 4 x 64: dot-product partials of the row waves
+  ldbl *tg;    // P x (P+1): T (upper, with diagonal) and G^T (strictly lower)
+  ldbl *top;   // P x (P+1): TSQRT block of R
+  ldbl *z;     // wide-T assembly product (aliases the panel phase)
+  int ibp, gmax;
+};
+
+template <int RW>
+__device__ inline Lds make_lds(double *lds_base, const MatDesc &m) {
+  using Gm = Geo<RW>;
   Lds L;
-  L.ldvc = lds_ldvc(mbt);
-  L.ibp = ib_pad16(ib);
-  L.gmax = gmax;
-  ldbl *p = (ldbl *)lds_base;
-  L.vc = p;
-  p += (int64_t)gmax * 16 * L.ldvc;
-  L.y = p;
-  p += nw * L.ibp * 16;
-  L.ts = p;
-  L.red1 = p;
-  p += 4;
-  L.red32 = p;
+  L.ibp = ib_pad16(m.ib);
+  L.gmax = m.gmax;
+  ldbl *base = (ldbl *)lds_base;
+  L.vc = base;
+  L.y = base + L.gmax * 16 * Gm::LDVC;
+  L.ts = L.y + Gm::CGN * L.ibp * 16;
+  ldbl *p = base;
+  L.vb = p;
+  p += 2 * Gm::ROWS;
+  L.taus = p;
+  p += 64;
+  L.red = p;
   p += 128;
-  L.tot = p;
-  p += 32;
-  L.scal = p;
-  p += 8;
-  L.tmm = p;
-  p += 32 * 33;
+  L.dred = p;
+  p += 256;
+  L.tg = p;
+  p += Gm::P * (Gm::P + 1);
   L.top = p;
+  L.z = base;
   return L;
 }
 
-// Width of the register-resident micro-panel in the panel kernels.
-constexpr int PWM = 16;
-
 // ---------------------------------------------------------------------------
-// Block-reflector application (LARFB / SSRFB bodies)
+// Block-reflector application (LARFB / SSRFB bodies, panel trailing updates)
 // ---------------------------------------------------------------------------
 
-// Stages chunks of V into LDS: columns gc0 .. gc0 + 16*ng of V (column c of
-// the group at L.vc + c*ldvc), rows 0..vrows rounded up to 16, zero outside
-// the reflector support. VK_UNIT: column gc has an implicit 1 at row gc and
-// 0 above. Four independent loads per thread are issued before their LDS
-// stores so that one memory latency covers them.
-template <int MBT>
-__device__ inline void load_vgroup(const Lds &L, const double *V, int64_t ldv, int vrows,
-                                   int kind, int gc0, int kvalid, int ng) {
-  constexpr int RP = MBT * 16;
+// V chunks [gc0, gc0 + 16*ng) (columns of V, rows 0 .. 128*RW) into per-lane
+// registers: element e = ebase + u*256 + tid sits at column e / ROWS, row
+// e % ROWS, so a lane walks one row (or two, ROWS = 512) and steps over
+// columns with a fixed stride; zero outside the reflector support. VK_UNIT:
+// column gc has an implicit 1 at row gc and 0 above.
+template <int RW>
+__device__ inline void vstage_load(double (&v)[PF], const double *V, int64_t ldv, int vrows,
+                                   int kind, int gc0, int kvalid, int ebase, int total) {
+  constexpr int ROWS = Geo<RW>::ROWS;
+  constexpr int CPU = ROWS <= NTHR ? NTHR / ROWS : 1;  // columns per step of u (ROWS <= 256)
+  const int tid = tid_x();
+  const int e0 = ebase + tid;
+  const int r0 = e0 % ROWS, c0 = gc0 + e0 / ROWS;
+  const gdbl *Vb = gp(V) + (int64_t)c0 * ldv + r0;
+#pragma unroll
+  for (int u = 0; u < PF; ++u) {
+    // ROWS = 512: u even -> rows r0, u odd -> rows r0 + 256 of the same column
+    const int du = ROWS <= NTHR ? u * CPU : u >> 1;
+    const int dr = ROWS <= NTHR ? 0 : (u & 1) * NTHR;
+    const int e = e0 + u * NTHR;
+    const int r = r0 + dr, gc = c0 + du;
+    double x = 0.0;
+    if (e < total && r < vrows && gc < kvalid) {
+      const double val = Vb[(int64_t)du * ldv + dr];
+      x = (kind == VK_UNIT) ? (r < gc ? 0.0 : (r == gc ? 1.0 : val)) : val;
+    }
+    v[u] = x;
+  }
+}
+
+// Registers of vstage_load into the LDS chunks (chunk-relative column c at
+// c * ldvc), rows up to vrows rounded to 16 (the zero padding of the last
+// row tile).
+template <int RW>
+__device__ inline void vstage_store(const Lds &L, const double (&v)[PF], int vrows, int ebase,
+                                    int total) {
+  constexpr int ROWS = Geo<RW>::ROWS, LDVC = Geo<RW>::LDVC;
+  constexpr int CPU = ROWS <= NTHR ? NTHR / ROWS : 1;
   const int rlim = (vrows + 15) & ~15;
-  const int total = ng * 16 * RP;
-  const gdbl *Vg = gp(V);
-  for (int base = 0; base < total; base += NTHR * 4) {
-    double v[4];
+  const int e0 = ebase + tid_x();
+  const int r0 = e0 % ROWS, c0 = e0 / ROWS;
+  ldbl *lb = L.vc + c0 * LDVC + r0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = base + u * NTHR + threadIdx.x;
-      const int c = e / RP, r = e % RP;
-      const int gc = gc0 + c;
-      double x = 0.0;
-      if (e < total && r < vrows && gc < kvalid) {
-        if (kind == VK_UNIT)
-          x = r < gc ? 0.0 : (r == gc ? 1.0 : Vg[r + (int64_t)gc * ldv]);
-        else
-          x = Vg[r + (int64_t)gc * ldv];
-      }
-      v[u] = x;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = base + u * NTHR + threadIdx.x;
-      const int c = e / RP, r = e % RP;
-      if (e < total && r < rlim) L.vc[c * L.ldvc + r] = v[u];
-    }
+  for (int u = 0; u < PF; ++u) {
+    const int du = ROWS <= NTHR ? u * CPU : u >> 1;
+    const int dr = ROWS <= NTHR ? 0 : (u & 1) * NTHR;
+    if (e0 + u * NTHR < total && r0 + dr < rlim) lb[du * LDVC + dr] = v[u];
+  }
+}
+
+// Chunks [gc0, gc0 + 16*ng) of V straight into LDS.
+template <int RW>
+__device__ inline void stage_v(const Lds &L, const double *V, int64_t ldv, int vrows, int kind,
+                               int gc0, int kvalid, int ng) {
+  const int total = ng * 16 * Geo<RW>::ROWS;
+  for (int base = 0; base < total; base += PF * NTHR) {
+    double v[PF];
+    vstage_load<RW>(v, V, ldv, vrows, kind, gc0, kvalid, base, total);
+    vstage_store<RW>(L, v, vrows, base, total);
   }
 }
 
 // T_s (ibw x ibw upper triangle of the block at Tb, leading dimension ldt)
-// into L.ts as [a * (ibp + 1) + c], zero elsewhere up to ibp x ibp, where ibp
-// is the padded inner block of the application in progress (not the task's).
-__device__ inline void load_tblock(const Lds &L, const double *Tb, int64_t ldt, int ibw, int ibp) {
-  const int total = ibp * ibp, ldts = lds_ldts(ibp);
+// as ibp x ibp with zeros elsewhere (ibp <= TQ_TS_MAX); element
+// e = u*256 + tid at (a = e / TQ_TS_MAX, c = e % TQ_TS_MAX).
+constexpr int TPF = TQ_TS_MAX * TQ_TS_MAX / NTHR;
+__device__ inline void tstage_load(double (&v)[TPF], const double *Tb, int64_t ldt, int ibw) {
   const gdbl *Tg = gp(Tb);
-  for (int base = 0; base < total; base += NTHR * 4) {
-    double v[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = base + u * NTHR + threadIdx.x;
-      const int a = e / ibp, c = e % ibp;
-      v[u] = (e < total && a <= c && c < ibw) ? Tg[a + (int64_t)c * ldt] : 0.0;
-    }
+  for (int u = 0; u < TPF; ++u) {
+    const int e = u * NTHR + tid_x();
+    const int a = e / TQ_TS_MAX, c = e % TQ_TS_MAX;
+    v[u] = (a <= c && c < ibw) ? Tg[a + (int64_t)c * ldt] : 0.0;
+  }
+}
+__device__ inline void tstage_store(const Lds &L, const double (&v)[TPF], int ibp) {
+  const int ldts = ibp + 1;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = base + u * NTHR + threadIdx.x;
-      if (e < total) L.ts[(e / ibp) * ldts + (e % ibp)] = v[u];
-    }
+  for (int u = 0; u < TPF; ++u) {
+    const int e = u * NTHR + tid_x();
+    const int a = e / TQ_TS_MAX, c = e % TQ_TS_MAX;
+    if (a < ibp && c < ibp) L.ts[a * ldts + c] = v[u];
   }
 }
 
-// C[0..crows) x column `col` into the accumulator layout of the FP64 MFMA:
-// tile rt, register r holds row 16*rt + 4*r + lane/16 (column lane%16).
-// VK_UNIT applies the unit-lower mask of a reflector whose head row is
-// diag + col.
-template <int MBT>
-__device__ inline void load_c2(d4 (&c2)[MBT], const double *C, int64_t ldc, int crows, int col,
-                               bool colok, int kind, int diag) {
-  const int g = lane_id() >> 4;
-  const gdbl *Cg = gp(C);
+// C1 rows [s, s + ibw) of the wave's 16 columns (column group cg), element
+// e = u*64 + lane at (a = e / 16, c = e % 16); ibw <= 32.
+constexpr int CPF = TQ_TS_MAX * 16 / 64;
+__device__ inline void c1_load(double (&v)[CPF], const double *C1, int64_t ldc1, int s, int ibw,
+                               int ncols, int cg) {
+  const int ln = lane_id();
+  const int c = cg * 16 + (ln & 15);
+  const gdbl *Cb = gp(C1) + (int64_t)c * ldc1 + s + (ln >> 4);
 #pragma unroll
-  for (int rt = 0; rt < MBT; ++rt) {
+  for (int u = 0; u < CPF; ++u) {
+    const int a = 4 * u + (ln >> 4);
+    v[u] = (a < ibw && c < ncols) ? Cb[4 * u] : 0.0;
+  }
+}
+
+// C[rbase + 0 .. 128) x column `col` into the accumulator layout.
+__device__ inline void load_c2(d4 (&c2)[RT], const double *C, int64_t ldc, int crows, int col,
+                               bool colok, int rbase) {
+  const int g = lane_id() >> 4;
+  const gdbl *Cb = gp(C) + (int64_t)col * ldc + rbase + g;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = rt * 16 + 4 * r + g;
-      double v = 0.0;
-      if (colok && row < crows) {
-        if (kind == VK_UNIT) {
-          const int h = diag + col;
-          v = row < h ? 0.0 : (row == h ? 1.0 : Cg[row + (int64_t)col * ldc]);
-        } else {
-          v = Cg[row + (int64_t)col * ldc];
-        }
-      }
-      c2[rt][r] = v;
+      const int row = rbase + rt * 16 + 4 * r + g;
+      c2[rt][r] = (colok && row < crows) ? Cb[rt * 16 + 4 * r] : 0.0;
     }
   }
 }
 
-template <int MBT>
-__device__ inline void store_c2(const d4 (&c2)[MBT], double *C, int64_t ldc, int crows, int col,
-                                bool colok) {
+__device__ inline void store_c2(const d4 (&c2)[RT], double *C, int64_t ldc, int crows, int col,
+                                bool colok, int rbase) {
   if (!colok) return;
   const int g = lane_id() >> 4;
-  gdbl *Cg = gp(C);
+  gdbl *Cb = gp(C) + (int64_t)col * ldc + rbase + g;
 #pragma unroll
-  for (int rt = 0; rt < MBT; ++rt) {
-    if (rt * 16 >= crows) break;
+  for (int rt = 0; rt < RT; ++rt) {
+    if (rbase + rt * 16 >= crows) break;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = rt * 16 + 4 * r + g;
-      if (row < crows) Cg[row + (int64_t)col * ldc] = c2[rt][r];
+      const int row = rbase + rt * 16 + 4 * r + g;
+      if (row < crows) Cb[rt * 16 + 4 * r] = c2[rt][r];
     }
   }
 }
 
-// Y rows of the staged chunks (group starting at chunk g0 of the block whose
-// first reflector is s): Y[q] = V[:, s+16q..]^T C2 -> wave region yw. The B
-// operand is accumulator register r of C2 tile rt (k index lane/16 <-> row
-// 16*rt + 4*r + lane/16); the A operand is V^T at those rows.
-template <int MBT>
-__device__ inline void y_group(const Lds &L, int kind, int s, int g0, int ng, int vrows,
-                               const d4 (&c2)[MBT], ldbl *yw) {
+// First row tile of the wave block that can hold a nonzero of the staged
+// chunk q of the block starting at reflector s (unit-lower V: rows above
+// s + 16q are zero).
+__device__ inline int first_rt(int kind, int s, int q, int rbase) {
+  if (kind != VK_UNIT) return 0;
+  const int d = s + q * 16 - rbase;
+  return d > 0 ? (d >> 4) : 0;
+}
+
+// Y rows of the staged chunks [g0, g0+ng) (chunk g0 + g is block chunk q):
+// Y[q] (+)= V[:, s+16q ..]^T C2 over the wave's rows, into the group region
+// yw. The B operand is accumulator register r of C2 tile rt (k index
+// lane/16 <-> row 16*rt + 4*r + lane/16); the A operand is V^T at those rows.
+template <int RW>
+__device__ inline void y_group(const Lds &L, int kind, int s, int q0, int ng, int vrows,
+                               const d4 (&c2)[RT], ldbl *yw, int rbase, bool acc) {
+  constexpr int LDVC = Geo<RW>::LDVC;
   const int ln = lane_id();
   for (int g = 0; g < ng; ++g) {
-    const int q = g0 + g;
+    const int q = q0 + g;
     d4 y0 = {0.0, 0.0, 0.0, 0.0}, y1 = {0.0, 0.0, 0.0, 0.0};
-    const int rt0 = (kind == VK_UNIT) ? ((s + q * 16) >> 4) : 0;
-    const ldbl *vp = L.vc + (g * 16 + (ln & 15)) * L.ldvc + (ln >> 4);
+    const int rt0 = first_rt(kind, s, q, rbase);
+    const ldbl *vp = L.vc + (g * 16 + (ln & 15)) * LDVC + rbase + (ln >> 4);
 #pragma unroll
-    for (int rt = 0; rt < MBT; ++rt) {
-      if (rt >= rt0 && rt * 16 < vrows) {
+    for (int rt = 0; rt < RT; ++rt) {
+      if (rt >= rt0 && rbase + rt * 16 < vrows) {
         y0 = mfma(vp[rt * 16 + 0], c2[rt][0], y0);
         y1 = mfma(vp[rt * 16 + 4], c2[rt][1], y1);
         y0 = mfma(vp[rt * 16 + 8], c2[rt][2], y0);
@@ -233,35 +311,41 @@ __device__ inline void y_group(const Lds &L, int kind, int s, int g0, int ng, in
       }
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      yw[(q * 16 + 4 * r + (ln >> 4)) * 16 + (ln & 15)] = y0[r] + y1[r];
+    for (int r = 0; r < 4; ++r) {
+      ldbl *d = yw + (q * 16 + 4 * r + (ln >> 4)) * 16 + (ln & 15);
+      if (acc)
+        *d += y0[r] + y1[r];
+      else
+        *d = y0[r] + y1[r];
+    }
   }
 }
 
-// C2 -= V_s W for the staged chunks: A = -V[row 16*rt + lane%16][col 4kk +
-// lane/16 of chunk q], B = W[16q + 4kk + lane/16][lane%16].
-template <int MBT>
-__device__ inline void update_group(const Lds &L, int kind, int s, int g0, int ng, int vrows,
-                                    const ldbl *yw, d4 (&c2)[MBT]) {
+// C2 -= V_s W over the wave's rows for the staged chunks: A = -V[row 16*rt +
+// lane%16][col 4kk + lane/16 of chunk q], B = W[16q + 4kk + lane/16][lane%16].
+template <int RW>
+__device__ inline void update_group(const Lds &L, int kind, int s, int q0, int ng, int vrows,
+                                    const ldbl *yw, d4 (&c2)[RT], int rbase) {
+  constexpr int LDVC = Geo<RW>::LDVC;
   const int ln = lane_id();
   for (int g = 0; g < ng; ++g) {
-    const int q = g0 + g;
-    const int rt0 = (kind == VK_UNIT) ? ((s + q * 16) >> 4) : 0;
+    const int q = q0 + g;
+    const int rt0 = first_rt(kind, s, q, rbase);
     double b[4];
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) b[kk] = yw[(q * 16 + 4 * kk + (ln >> 4)) * 16 + (ln & 15)];
-    const ldbl *vp = L.vc + (g * 16 + (ln >> 4)) * L.ldvc + (ln & 15);
+    const ldbl *vp = L.vc + (g * 16 + (ln >> 4)) * LDVC + rbase + (ln & 15);
 #pragma unroll
-    for (int rt = 0; rt < MBT; ++rt) {
-      if (rt >= rt0 && rt * 16 < vrows) {
+    for (int rt = 0; rt < RT; ++rt) {
+      if (rt >= rt0 && rbase + rt * 16 < vrows) {
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) c2[rt] = mfma(-vp[4 * kk * L.ldvc + rt * 16], b[kk], c2[rt]);
+        for (int kk = 0; kk < 4; ++kk) c2[rt] = mfma(-vp[4 * kk * LDVC + rt * 16], b[kk], c2[rt]);
       }
     }
   }
 }
 
-// W = T_s^T Ytot in place in the wave region, bottom block first (W block q
+// W = T_s^T Ytot in place in the group region, bottom block first (W block q
 // needs Y blocks <= q). T_s from the LDS stage or from global memory.
 template <bool TLDS>
 __device__ inline void w_phase(const Lds &L, const double *Ts, int64_t ldt, int ibw, int ldts,
@@ -284,16 +368,18 @@ __device__ inline void w_phase(const Lds &L, const double *Ts, int64_t ldt, int 
         w = mfma(a, yw[arow * 16 + (ln & 15)], w);
       }
     }
+    wave_sync();
 #pragma unroll
     for (int r = 0; r < 4; ++r) yw[(q * 16 + 4 * r + (ln >> 4)) * 16 + (ln & 15)] = w[r];
+    wave_sync();
   }
 }
 
-// yw[a][c] += C1[s + a][col c] (add = true) or C1 -= yw (add = false) for the
-// wave's columns; loads batched four per lane.
+// yw[a][c] += C1[s + a][col c] (add) or C1 = C1 - yw (sub) for the wave's
+// column group, straight from global memory.
 __device__ inline void c1_pass(ldbl *yw, double *C1, int64_t ldc1, int s, int ibw, int ncols,
-                               bool add) {
-  const int ln = lane_id(), wv = wave_id();
+                               int cg, bool add) {
+  const int ln = lane_id();
   gdbl *Cg = gp(C1);
   const int total = ibw * 16;
   for (int base = 0; base < total; base += 64 * 4) {
@@ -301,13 +387,13 @@ __device__ inline void c1_pass(ldbl *yw, double *C1, int64_t ldc1, int s, int ib
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int e = base + u * 64 + ln;
-      const int a = e >> 4, c = wv * 16 + (e & 15);
+      const int a = e >> 4, c = cg * 16 + (e & 15);
       v[u] = (e < total && c < ncols) ? Cg[(s + a) + (int64_t)c * ldc1] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int e = base + u * 64 + ln;
-      const int a = e >> 4, c = wv * 16 + (e & 15);
+      const int a = e >> 4, c = cg * 16 + (e & 15);
       if (e < total) {
         if (add)
           yw[e] += v[u];
@@ -319,82 +405,133 @@ __device__ inline void c1_pass(ldbl *yw, double *C1, int64_t ldc1, int s, int ib
 }
 
 // Applies the reflectors V[:, 0..kref) (blocks of ib, compact-WY factors in
-// T: block s at T + s*ldt) to one strip of at most 16*nw columns:
-//   C1 (optional): rows s..s+ib of the block's top part, C2: vrows rows.
-// Per block: stage V_s (and T_s) in LDS once, Y = V_s^T C2 + C1_s,
-// W = T_s^T Y, C1_s -= W, C2 -= V_s W.
-//
-// yonly: stop after Y of the first block (Y left in the wave region), with C2
-// read as reflectors (unit-lower with head row c2diag + col if c2diag >= 0,
-// full otherwise): the Gram product of the T assembly; nothing is written.
-template <int MBT>
+// T: block s at T + s*ldt) to one strip of at most 16 * (4 / RW) columns:
+//   C1 (optional): rows s .. s+ib of the block's top part, C2: vrows rows.
+// Per block: stage V_s (and T_s) in LDS, Y = V_s^T C2 + C1_s (row waves add
+// their slabs one after the other), W = T_s^T Y, C1_s -= W, C2 -= V_s W.
+template <int RW>
 __device__ __forceinline__ void apply_strip(const Lds &L, const double *V, int64_t ldv, int vrows,
                                             int kind, int kref, int ib, const double *T,
                                             int64_t ldt, double *C1, int64_t ldc1, double *C2,
-                                            int64_t ldc2, int ncols, int nw, bool yonly,
-                                            int c2diag) {
+                                            int64_t ldc2, int ncols) {
+  constexpr int ROWS = Geo<RW>::ROWS;
   const int ln = lane_id(), wv = wave_id();
-  const bool active = (wv < nw) && (wv * 16 < ncols);
-  const int col = wv * 16 + (ln & 15);
-  const bool colok = active && col < ncols;
-  d4 c2[MBT];
-  load_c2<MBT>(c2, C2, ldc2, vrows, col, colok, (yonly && c2diag >= 0) ? VK_UNIT : VK_FULL,
-               c2diag);
-  ldbl *yw = L.y + wv * L.ibp * 16;
-  // T_s staged in LDS when the block is narrow enough; the stage region is
-  // sized for the task's inner block and for the panel scratch, so any
-  // application with ib_pad16(ib) <= 64 fits.
+  const int cg = wv / RW, rb = wv % RW, rbase = rb * TQ_ROWS_PER_WAVE;
+  const bool gact = cg * 16 < ncols;  // wave-uniform
+  const int col = cg * 16 + (ln & 15);
+  const bool colok = col < ncols;
+  const int ibp = ib_pad16(ib), ldts = ibp + 1;
   const bool tl = t_in_lds(ib);
-  const int ibp_a = ib_pad16(ib), ldts_a = lds_ldts(ibp_a);
+  const int nqb = ibp >> 4;
+  // Register pipeline: the whole block fits the staged chunks and the
+  // prefetch registers, and T_s the LDS stage.
+  const bool pf = tl && nqb <= L.gmax && nqb * 16 * ROWS <= PF * NTHR;
+  ldbl *yw = L.y + cg * L.ibp * 16;
+  const bool c1w = C1 != nullptr && rb == 0 && gact;
+  d4 c2[RT];
+  load_c2(c2, C2, ldc2, vrows, col, colok && gact, rbase);
+  double pv[PF], pt[TPF], pc[CPF];
+  if (pf) {
+    const int ibw0 = min(ib, kref);
+    vstage_load<RW>(pv, V, ldv, vrows, kind, 0, ibw0, 0, ((ibw0 + 15) >> 4) * 16 * ROWS);
+    tstage_load(pt, T, ldt, ibw0);
+    if (c1w) c1_load(pc, C1, ldc1, 0, ibw0, ncols, cg);
+  }
   for (int s = 0; s < kref; s += ib) {
     const int ibw = min(ib, kref - s);
     const int nq = (ibw + 15) >> 4;
     const bool resident = nq <= L.gmax;
+    const int sn = s + ib;
+    // --- Y = V_s^T C2 ---
     for (int g0 = 0; g0 < nq; g0 += L.gmax) {
       const int ng = min(L.gmax, nq - g0);
       __syncthreads();
-      load_vgroup<MBT>(L, V, ldv, vrows, kind, s + g0 * 16, s + ibw, ng);
-      if (g0 == 0 && tl && !yonly) load_tblock(L, T + (int64_t)s * ldt, ldt, ibw, ibp_a);
+      if (pf) {
+        vstage_store<RW>(L, pv, vrows, 0, nq * 16 * ROWS);
+        tstage_store(L, pt, ibp);
+        if (sn < kref) {
+          const int ibwn = min(ib, kref - sn);
+          vstage_load<RW>(pv, V, ldv, vrows, kind, sn, sn + ibwn, 0,
+                          ((ibwn + 15) >> 4) * 16 * ROWS);
+          tstage_load(pt, T + (int64_t)sn * ldt, ldt, ibwn);
+        }
+      } else {
+        stage_v<RW>(L, V, ldv, vrows, kind, s + g0 * 16, s + ibw, ng);
+        if (g0 == 0 && tl) {
+          double t[TPF];
+          tstage_load(t, T + (int64_t)s * ldt, ldt, ibw);
+          tstage_store(L, t, ibp);
+        }
+      }
       __syncthreads();
-      if (active) y_group<MBT>(L, kind, s, g0, ng, vrows, c2, yw);
+      for (int rr = 0; rr < RW; ++rr) {
+        if (rr > 0) __syncthreads();
+        if (rb == rr && gact) y_group<RW>(L, kind, s, g0, ng, vrows, c2, yw, rbase, rr > 0);
+      }
     }
-    __syncthreads();
-    if (yonly) return;
-    if (active && C1) c1_pass(yw, C1, ldc1, s, ibw, ncols, true);
-    __syncthreads();
-    if (active) {
+    if (RW > 1) __syncthreads();
+    // --- Y += C1_s; W = T_s^T Y; C1_s -= W (first row wave of each group) ---
+    if (c1w) {
+      if (pf) {
+#pragma unroll
+        for (int u = 0; u < CPF; ++u) {
+          const int e = u * 64 + ln;
+          if (e < ibw * 16) yw[e] += pc[u];
+        }
+      } else {
+        c1_pass(yw, C1, ldc1, s, ibw, ncols, cg, true);
+      }
+    }
+    if (rb == 0 && gact) {
+      wave_sync();
       if (tl)
-        w_phase<true>(L, nullptr, 0, ibw, ldts_a, yw);
+        w_phase<true>(L, nullptr, 0, ibw, ldts, yw);
       else
-        w_phase<false>(L, T + (int64_t)s * ldt, ldt, ibw, ldts_a, yw);
+        w_phase<false>(L, T + (int64_t)s * ldt, ldt, ibw, ldts, yw);
     }
-    __syncthreads();
-    if (active && C1) c1_pass(yw, C1, ldc1, s, ibw, ncols, false);
+    if (c1w) {
+      if (pf) {
+        gdbl *Cb = gp(C1) + (int64_t)col * ldc1 + s + (ln >> 4);
+#pragma unroll
+        for (int u = 0; u < CPF; ++u) {
+          const int a = 4 * u + (ln >> 4);
+          if (a < ibw && colok) Cb[4 * u] = pc[u] - yw[a * 16 + (ln & 15)];
+        }
+        if (sn < kref) c1_load(pc, C1, ldc1, sn, min(ib, kref - sn), ncols, cg);
+      } else {
+        c1_pass(yw, C1, ldc1, s, ibw, ncols, cg, false);
+      }
+    }
+    if (RW > 1)
+      __syncthreads();
+    else
+      wave_sync();
+    // --- C2 -= V_s W ---
     for (int g0 = 0; g0 < nq; g0 += L.gmax) {
       const int ng = min(L.gmax, nq - g0);
       if (!resident) {
         __syncthreads();
-        load_vgroup<MBT>(L, V, ldv, vrows, kind, s + g0 * 16, s + ibw, ng);
+        stage_v<RW>(L, V, ldv, vrows, kind, s + g0 * 16, s + ibw, ng);
         __syncthreads();
       }
-      if (active) update_group<MBT>(L, kind, s, g0, ng, vrows, yw, c2);
+      if (gact) update_group<RW>(L, kind, s, g0, ng, vrows, yw, c2, rbase);
     }
   }
   __syncthreads();
-  store_c2<MBT>(c2, C2, ldc2, vrows, col, colok);
+  store_c2(c2, C2, ldc2, vrows, col, colok && gact, rbase);
 }
 
-// All columns of C2 (and C1), in strips of 16*nw.
-template <int MBT>
-__device__ __forceinline__ void apply_cols(const Lds &L, const double *V, int64_t ldv, int vrows, int kind,
-                           int kref, int ib, const double *T, int64_t ldt, double *C1,
-                           int64_t ldc1, double *C2, int64_t ldc2, int ncols, int nw, bool yonly,
-                           int c2diag) {
-  const int w = 16 * nw;
+// All columns of C2 (and C1), in strips of 16 * (4 / RW).
+template <int RW>
+__device__ __forceinline__ void apply_cols(const Lds &L, const double *V, int64_t ldv, int vrows,
+                                           int kind, int kref, int ib, const double *T,
+                                           int64_t ldt, double *C1, int64_t ldc1, double *C2,
+                                           int64_t ldc2, int ncols) {
+  constexpr int w = Geo<RW>::P;
   for (int c0 = 0; c0 < ncols; c0 += w) {
-    apply_strip<MBT>(L, V, ldv, vrows, kind, kref, ib, T, ldt,
-                     C1 ? C1 + (int64_t)c0 * ldc1 : nullptr, ldc1, C2 + (int64_t)c0 * ldc2, ldc2,
-                     min(w, ncols - c0), nw, yonly, c2diag);
+    apply_strip<RW>(L, V, ldv, vrows, kind, kref, ib, T, ldt,
+                    C1 ? C1 + (int64_t)c0 * ldc1 : nullptr, ldc1, C2 + (int64_t)c0 * ldc2, ldc2,
+                    min(w, ncols - c0));
   }
   __syncthreads();
 }
@@ -418,378 +555,440 @@ __device__ inline void householder(double alpha, double ss, double &beta, double
   }
 }
 
-// Register slots rotate left once per column, so the current column is
-// always slot 0, the remaining ones slots 1..pw-1-c and the finished ones
-// slots PW-c..PW-1 (column p at slot PW-c+p).
-template <int HR, int PW>
-__device__ inline void rotate_slots(double (&x)[HR][PW]) {
+// C (m x n) = sum_k A(i, k) B(k, j) on the FP64 MFMA, 16 x 16 output tiles
+// spread over the waves; the operands come from functors that return 0
+// outside their ranges (four k-steps of loads are issued before their
+// MFMAs), the result goes to a functor per element.
+template <class FA, class FB, class FS>
+__device__ inline void small_gemm(int m, int n, int kd, FA fa, FB fb, FS fs) {
+  const int ln = lane_id(), wv = wave_id();
+  const int tm = (m + 15) >> 4, tn = (n + 15) >> 4;
+  for (int t = wv; t < tm * tn; t += 4) {
+    const int i0 = (t % tm) * 16, j0 = (t / tm) * 16;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < kd; k0 += 16) {
+      double av[4], bv[4];
 #pragma unroll
-  for (int h = 0; h < HR; ++h) {
-    const double t0 = x[h][0];
-#pragma unroll
-    for (int i = 0; i < PW - 1; ++i) x[h][i] = x[h][i + 1];
-    x[h][PW - 1] = t0;
-  }
-}
-
-__device__ inline void store_micro_T(const Lds &L, double *Tmm, int64_t ldt, int pw) {
-  __syncthreads();
-  gdbl *Tg = gp(Tmm);
-  for (int e = threadIdx.x; e < pw * pw; e += NTHR) {
-    const int a = e % pw, c = e / pw;
-    Tg[a + (int64_t)c * ldt] = a <= c ? L.tmm[a * 33 + c] : 0.0;
-  }
-  __syncthreads();
-}
-
-// Orders the wave's LDS accesses before this point against those after it
-// (the lanes of a wave run in lockstep; this pins the compiler's ordering).
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Wave-level sum of one double (xor butterfly; every lane gets the total).
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-
-// Wave-level sums of v[0..NV) (NV = 8 or 16) into slot[0..NV), an LDS slot
-// private to the calling wave; every lane then reads the totals it needs.
-// Each exchange step hands half of the remaining values to the partner lane,
-// so NV values cost NV - 1 shuffles instead of NV butterflies.
-template <int NV>
-__device__ inline void wave_sumN(ldbl *slot, const double (&v)[NV]) {
-  const int ln = lane_id();
-  double h[NV];
-#pragma unroll
-  for (int i = 0; i < NV; ++i) h[i] = v[i];
-  int n = NV;
-  int idx = 0;
-#pragma unroll
-  for (int bit = 5; bit >= 0; --bit) {
-    const int half = n >> 1;
-    if (half == 0) {
-      h[0] += __shfl_xor(h[0], 1 << bit);
-    } else {
-      const bool hi = (ln >> bit) & 1;
-#pragma unroll
-      for (int i = 0; i < NV / 2; ++i) {
-        if (i < half) {
-          const double snd = hi ? h[i] : h[half + i];
-          const double keep = hi ? h[half + i] : h[i];
-          h[i] = keep + __shfl_xor(snd, 1 << bit);
-        }
+      for (int u = 0; u < 4; ++u) {
+        const int kk = k0 + 4 * u + (ln >> 4);
+        av[u] = fa(i0 + (ln & 15), kk);
+        bv[u] = fb(kk, j0 + (ln & 15));
       }
-      idx = idx * 2 + (hi ? 1 : 0);
-      n = half;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = mfma(av[u], bv[u], acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) fs(i0 + 4 * r + (ln >> 4), j0 + (ln & 15), acc[r]);
+  }
+}
+
+// G = V[:, 0:a]^T V[:, a:a+pw] (pw <= one strip) into Tb[i + (a + j) * ldt]:
+// the Y phase of the block application with C2 = the reflectors [a, a+pw).
+template <int RW>
+__device__ __forceinline__ void gram_cross(const Lds &L, const double *V, int64_t ldv, int vrows, int kind, int a,
+                           int pw, double *Tb, int64_t ldt) {
+  const int ln = lane_id(), wv = wave_id();
+  const int cg = wv / RW, rb = wv % RW, rbase = rb * TQ_ROWS_PER_WAVE;
+  const int col = cg * 16 + (ln & 15);
+  const bool gact = cg * 16 < pw;
+  const gdbl *Vg = gp(V);
+  d4 c2[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = rbase + rt * 16 + 4 * r + (ln >> 4);
+      const int gc = a + col;
+      double v = 0.0;
+      if (col < pw && row < vrows) {
+        if (kind == VK_UNIT)
+          v = row < gc ? 0.0 : (row == gc ? 1.0 : Vg[row + (int64_t)gc * ldv]);
+        else
+          v = Vg[row + (int64_t)gc * ldv];
+      }
+      c2[rt][r] = v;
+    }
+  ldbl *yw = L.y + cg * L.ibp * 16;
+  const int nq = (a + 15) >> 4;
+  for (int g0 = 0; g0 < nq; g0 += L.gmax) {
+    const int ng = min(L.gmax, nq - g0);
+    __syncthreads();
+    stage_v<RW>(L, V, ldv, vrows, kind, g0 * 16, a, ng);
+    __syncthreads();
+    for (int rr = 0; rr < RW; ++rr) {
+      if (rr > 0) __syncthreads();
+      if (rb == rr && gact) y_group<RW>(L, kind, 0, g0, ng, vrows, c2, yw, rbase, rr > 0);
     }
   }
-  // Lanes sharing the low (6 - log2 NV) bits hold the same total, index idx.
-  constexpr int LOW = (NV == 16) ? 2 : 3;
-  if (!(ln & ((1 << LOW) - 1))) slot[idx] = h[0];
+  __syncthreads();
+  if (rb == 0 && gact) {
+    gdbl *Tg = gp(Tb);
+    for (int e = ln; e < a * 16; e += 64) {
+      const int i = e >> 4, c = cg * 16 + (e & 15);
+      if (c < pw) Tg[i + (int64_t)(a + c) * ldt] = yw[e];
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+}
+
+// Off-diagonal parts of the T factor of an IB block wider than a register
+// panel: the diagonal blocks of width P (one per register panel) are there;
+// for each later panel [a, a + pw) of the block,
+//   T[0:a, a:a+pw] = -T[0:a, 0:a] (V[:, 0:a]^T V[:, a:a+pw]) T[a:a+pw, a:a+pw].
+// V: the block's reflectors (unit lower from row 0 of the block frame for
+// GEQRT, full for TSQRT), Tb: the block's T (leading dimension ldt).
+template <int RW>
+__device__ __forceinline__ void assemble_wide_T(const Lds &L, const double *V, int64_t ldv, int vrows, int kind,
+                                int ibw, double *Tb, int64_t ldt) {
+  constexpr int P = Geo<RW>::P;
+  gdbl *Tg = gp(Tb);
+  for (int a = P; a < ibw; a += P) {
+    const int pw = min(P, ibw - a);
+    gram_cross<RW>(L, V, ldv, vrows, kind, a, pw, Tb, ldt);
+    // Z = G T[a:a+pw, a:a+pw] into LDS (a x pw, [i * pw + j])
+    ldbl *Z = L.z;
+    small_gemm(
+        a, pw, pw,
+        [=](int i, int k) { return (i < a && k < pw) ? (double)Tg[i + (int64_t)(a + k) * ldt] : 0.0; },
+        [=](int k, int j) {
+          return (k < pw && j < pw && k <= j) ? (double)Tg[(a + k) + (int64_t)(a + j) * ldt] : 0.0;
+        },
+        [=](int i, int j, double v) {
+          if (i < a && j < pw) Z[i * pw + j] = v;
+        });
+    __syncthreads();
+    // T[0:a, a:a+pw] = -T[0:a, 0:a] Z
+    small_gemm(
+        a, pw, a,
+        [=](int i, int k) {
+          return (i < a && k < a && i <= k) ? (double)Tg[i + (int64_t)k * ldt] : 0.0;
+        },
+        [=](int k, int j) { return (k < a && j < pw) ? (double)Z[k * pw + j] : 0.0; },
+        [=](int i, int j, double v) {
+          if (i < a && j < pw) Tg[i + (int64_t)(a + j) * ldt] = -v;
+        });
+    __threadfence_block();
+    __syncthreads();
+  }
+}
+
+// Column cc of the T block that starts at local column tb: lanes a in
+// [tb, cc) of the calling wave compute T[a][cc] = -tau_cc * sum_{p=a}^{cc-1}
+// T[a][p] G[p][cc]; lane cc sets T[cc][cc] = tau_cc. T is the upper part of
+// L.tg, G^T its strictly lower part.
+template <int RW>
+__device__ inline void t_column(const Lds &L, int cc, int tb) {
+  constexpr int ld = Geo<RW>::P + 1;
+  const int a = lane_id();
+  const double tau = L.taus[cc];
+  if (a >= tb && a < cc) {
+    double t0 = 0.0, t1 = 0.0;
+    int p = a;
+    for (; p + 1 < cc; p += 2) {
+      t0 += L.tg[a * ld + p] * L.tg[cc * ld + p];
+      t1 += L.tg[a * ld + p + 1] * L.tg[cc * ld + p + 1];
+    }
+    if (p < cc) t0 += L.tg[a * ld + p] * L.tg[cc * ld + p];
+    L.tg[a * ld + cc] = -tau * (t0 + t1);
+  }
+  if (a == cc) L.tg[cc * ld + cc] = tau;
   wave_sync();
 }
 
-// Unblocked Householder QR of one micro-panel of pw <= PW columns on ONE
-// wave (wave 0): lane l holds rows l, l+64, ... in registers, so every
-// reduction is wave-local and the column loop has no workgroup barrier.
-//  GEQRT (ts == false): X = P[0..mrows) x [m0, m0+pw) in the block frame;
-//    reflector c has its unit at row m0+c, zeros above.
-//  TSQRT (ts == true): X = U[0..mrows) x [0, pw) under the pw x pw upper
-//    block of R kept in L.top; reflector c is [e_c; u_c].
-// Each column costs one reduction for the norm and one batched reduction for
-// all its dot products (remaining columns: the update; finished columns: the
-// Gram entries that build column c of the micro-panel's T). Waves 1..3 wait
-// at the closing barrier.
-template <int HRW, int PW>
-__device__ __forceinline__ void level2_panel(const Lds &L, bool ts, double *X, int64_t ldx,
-                                             int mrows, int m0, int pw, double *Tmm, int64_t ldt) {
-  if (wave_id() == 0) {
-    const int ln = lane_id();
-    gdbl *Xg = gp(X);
-    double x[HRW][PW];
-#pragma unroll
-    for (int h = 0; h < HRW; ++h) {
-      const int row = ln + 64 * h;
-#pragma unroll
-      for (int i = 0; i < PW; ++i)
-        x[h][i] = (i < pw && row < mrows) ? Xg[row + (int64_t)(m0 + i) * ldx] : 0.0;
-    }
-    for (int c = 0; c < pw; ++c) {
-      const int jr = ts ? -1 : m0 + c;  // rows > jr form the reflector tail
-      double ss = 0.0, own = x[0][0];
-#pragma unroll
-      for (int h = 0; h < HRW; ++h) {
-        const int row = ln + 64 * h;
-        if (row > jr) ss += x[h][0] * x[h][0];
-        if (h > 0 && (jr >> 6) == h) own = x[h][0];
-      }
-      ss = wave_sum(ss);
-      const double alpha = ts ? L.top[c * 33 + c] : __shfl(own, jr & 63);
-      double beta, tau, scale;
-      householder(alpha, ss, beta, tau, scale);
-      double v[HRW];
-#pragma unroll
-      for (int h = 0; h < HRW; ++h) {
-        const int row = ln + 64 * h;
-        if (row > jr) {
-          x[h][0] *= scale;
-          v[h] = x[h][0];
-        } else if (row == jr) {
-          v[h] = 1.0;
-          x[h][0] = beta;
-        } else {
-          v[h] = 0.0;
-        }
-      }
-      double d[PW];
-      d[0] = 0.0;
-#pragma unroll
-      for (int i = 1; i < PW; ++i) {
-        double a = 0.0;
-#pragma unroll
-        for (int h = 0; h < HRW; ++h) a += v[h] * x[h][i];
-        d[i] = a;
-      }
-      ldbl *tot = L.tot;
-      wave_sumN<PW>(tot, d);
-      const int nrem = pw - 1 - c;
-      if (ts) {
-        // Remaining columns' dot products include row c of R; then row c of
-        // R is updated.
-        if (ln >= 1 && ln <= nrem) tot[ln] += L.top[c * 33 + c + ln];
-        wave_sync();
-        if (ln >= 1 && ln <= nrem) L.top[c * 33 + c + ln] -= tau * tot[ln];
-        if (ln == 0) L.top[c * 33 + c] = beta;
-      }
-#pragma unroll
-      for (int i = 1; i < PW; ++i) {
-        if (i <= nrem) {
-          const double f = tau * tot[i];
-#pragma unroll
-          for (int h = 0; h < HRW; ++h) x[h][i] -= f * v[h];
-        }
-      }
-      // T column c from the Gram entries of the finished columns (slot
-      // PW-c+p holds column p < c).
-      if (ln < c) {
-        double tval = 0.0;
-        for (int p = ln; p < c; ++p) tval += L.tmm[ln * 33 + p] * tot[PW - c + p];
-        L.tmm[ln * 33 + c] = -tau * tval;
-      }
-      if (ln == 0) L.tmm[c * 33 + c] = tau;
-      wave_sync();
-      rotate_slots<HRW, PW>(x);
-    }
-#pragma unroll
-    for (int h = 0; h < HRW; ++h) {
-      const int row = ln + 64 * h;
-#pragma unroll
-      for (int i = 0; i < PW; ++i) {
-        const int p = (i + pw) & (PW - 1);
-        if (p < pw && row < mrows) Xg[row + (int64_t)(m0 + p) * ldx] = x[h][i];
-      }
-    }
-  }
-  store_micro_T(L, Tmm, ldt, pw);
-}
+// GEQRT(k) (ts = false): QR of the diagonal tile in place.
+// TSQRT(i, k) (ts = true): QR of [R_kk; A_ik]: R_kk updated in place, A_ik
+// overwritten by the lower parts of the reflectors [e_j; u_j].
+// Columns are taken in register panels of at most P = 16 * (4 / RW) columns
+// that never straddle an IB block unless IB > P.
+template <int RW>
+__device__ __forceinline__ void panel_task(const MatDesc &m, const Lds &L, bool ts, int i, int k) {
+  constexpr int ROWS = Geo<RW>::ROWS, P = Geo<RW>::P, ld = P + 1;
+  const int nb = m.nb, ib = m.ib;
+  const int64_t lda = m.lda;
+  double *R = m.A + (int64_t)k * nb * lda + (int64_t)k * nb;
+  double *X = ts ? m.A + (int64_t)k * nb * lda + (int64_t)i * nb : R;
+  double *Tp = m.T + ((int64_t)k * m.MT + (ts ? i : k)) * (int64_t)ib * nb;
+  const int mrows = ts ? tile_rows(m, i) : tile_rows(m, k);
+  const int ncol = tile_cols(m, k);
+  const int K = ts ? ncol : min(mrows, ncol);
+  const int ln = lane_id(), wv = wave_id();
+  const int cg = wv / RW, rb = wv % RW, rbase = rb * TQ_ROWS_PER_WAVE;
+  const int mc = cg * 16 + (ln & 15);  // my column within the register panel
+  const int g4 = ln >> 4;
+  gdbl *Xg = gp(X);
+  gdbl *Rg = gp(R);
+  gdbl *Tg = gp(Tp);
 
-// After micro-panel [m0, m0+pw) of an IB block, with the Gram block
-// G = V[:, 0:m0]^T V[:, m0:m0+pw] already in the wave-0 region of L.y:
-// T[0:m0, m0:m0+pw] = -T[0:m0, 0:m0] G T[m0:, m0:], lower block zeroed.
-__device__ inline void assemble_T_post(const Lds &L, int m0, int pw, double *Tb, int64_t ldt) {
-  ldbl *G = L.y;  // wave 0 region: G[a*16 + c]
-  gdbl *Tg = gp(Tb);
-  for (int a = threadIdx.x; a < m0; a += NTHR) {
-    for (int c = pw - 1; c >= 0; --c) {
-      double acc = 0.0;
-      for (int p = 0; p <= c; ++p) acc += G[a * 16 + p] * Tg[(m0 + p) + (int64_t)(m0 + c) * ldt];
-      G[a * 16 + c] = acc;
+  int pw = 0;
+  for (int c0 = 0; c0 < K; c0 += pw) {
+    const int sg = (c0 / ib) * ib;
+    pw = ib <= P ? min(K - c0, (P / ib) * ib) : min(P, min(sg + ib, K) - c0);
+    const bool colok = mc < pw;
+    d4 x[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rbase + rt * 16 + 4 * r + g4;
+        x[rt][r] = (colok && row < mrows) ? Xg[row + (int64_t)(c0 + mc) * lda] : 0.0;
+      }
+    if (ts) {
+      for (int e = tid_x(); e < P * P; e += NTHR) {
+        const int a = e / P, c = e % P;
+        L.top[a * ld + c] = (a <= c && c < pw) ? Rg[(c0 + a) + (int64_t)(c0 + c) * lda] : 0.0;
+      }
+    }
+    __syncthreads();
+    for (int c = 0; c < pw; ++c) {
+      // lane-derived values recomputed per column (kept out of the loop's
+      // live registers; see tid_x)
+      const int g4 = lane_id() >> 4;
+      const int mc = cg * 16 + (lane_id() & 15);
+      const int j = c0 + c;
+      const int h = ts ? -1 : j;  // rows > h form the reflector tail
+      const int par = c & 1;
+      const bool owner = cg == (c >> 4);
+      const bool mine = (lane_id() & 15) == (c & 15);
+      // --- norm of the tail and alpha (owner column group) ---
+      double ss = 0.0, al = 0.0, alpha = 0.0;
+      if (owner) {
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = rbase + rt * 16 + 4 * r + g4;
+            const double v = x[rt][r];
+            ss += row > h ? v * v : 0.0;
+            al += row == h ? v : 0.0;
+          }
+        ss = col_sum(ss);
+        al = col_sum(al);
+        if (ts) alpha = L.top[c * ld + c];
+        if (RW > 1 && mine && g4 == 0) {
+          L.red[2 * rb] = ss;
+          L.red[2 * rb + 1] = al;
+        }
+      }
+      if (RW > 1) {
+        __syncthreads();
+        if (owner) {
+          ss = 0.0;
+          al = 0.0;
+          for (int q = 0; q < RW; ++q) {
+            ss += L.red[2 * q];
+            al += L.red[2 * q + 1];
+          }
+        }
+      }
+      // --- reflector: v in registers and in the broadcast buffer ---
+      if (owner) {
+        double beta, tau, scale;
+        householder(ts ? alpha : al, ss, beta, tau, scale);
+        wave_sync();  // every lane has read alpha before R_jj is overwritten
+        if (mine) {
+          ldbl *vb = L.vb + par * ROWS;
+#pragma unroll
+          for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = rbase + rt * 16 + 4 * r + g4;
+              const double xv = x[rt][r];
+              const double v = row > h ? xv * scale : (row == h ? 1.0 : 0.0);
+              x[rt][r] = row > h ? v : (row == h ? beta : xv);
+              vb[row] = v;
+            }
+          if (g4 == 0 && rb == 0) {
+            L.taus[c] = tau;
+            if (ts) L.top[c * ld + c] = beta;
+          }
+        }
+      }
+      __syncthreads();
+      // --- dot products of every column with v ---
+      const double tau = L.taus[c];
+      const ldbl *vb = L.vb + par * ROWS + rbase + g4;
+      double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        d0 += x[rt][0] * vb[rt * 16 + 0] + x[rt][2] * vb[rt * 16 + 8];
+        d1 += x[rt][1] * vb[rt * 16 + 4] + x[rt][3] * vb[rt * 16 + 12];
+      }
+      double d = col_sum(d0 + d1);
+      const bool active = mc > c && mc < pw;
+      const double rtop = (ts && active) ? L.top[c * ld + mc] : 0.0;
+      wave_sync();  // R_j row read by every lane of the column before it is written
+      if (RW > 1) {
+        if (g4 == 0) L.dred[rb * 64 + mc] = d;
+        __syncthreads();
+        d = 0.0;
+        for (int q = 0; q < RW; ++q) d += L.dred[q * 64 + mc];
+      }
+      if (active) {
+        d += rtop;
+        const double f = tau * d;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) x[rt][r] -= f * vb[rt * 16 + 4 * r];
+        if (ts && g4 == 0 && rb == 0) L.top[c * ld + mc] = rtop - f;
+      }
+      // Gram entry G[mc][c] of two reflectors of the same T block
+      const int tbc = ib <= P ? (j / ib) * ib - c0 : 0;
+      if (mc < c && mc >= tbc && g4 == 0 && rb == 0) L.tg[c * ld + mc] = d;
+      // T column c-1, one column behind the factorization
+      if (wv == 0 && c > 0) t_column<RW>(L, c - 1, ib <= P ? ((j - 1) / ib) * ib - c0 : 0);
+    }
+    __syncthreads();
+    if (wv == 0) t_column<RW>(L, pw - 1, ib <= P ? ((c0 + pw - 1) / ib) * ib - c0 : 0);
+    // --- write back the panel: R above, reflectors below ---
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rbase + rt * 16 + 4 * r + g4;
+        if (colok && row < mrows) Xg[row + (int64_t)(c0 + mc) * lda] = x[rt][r];
+      }
+    __syncthreads();
+    if (ts) {
+      for (int e = tid_x(); e < pw * pw; e += NTHR) {
+        const int a = e / pw, c = e % pw;
+        if (a <= c) Rg[(c0 + a) + (int64_t)(c0 + c) * lda] = L.top[a * ld + c];
+      }
+    }
+    // T of the panel's columns: whole blocks (IB <= P) or the diagonal block
+    // of this panel and the zeros below it (IB > P).
+    {
+      const int rlo = ib <= P ? 0 : c0 - sg;
+      const int bw = min(ib, K - sg);  // rows of the (last) block
+      const int span = ib <= P ? ib : bw - rlo;
+      for (int e = tid_x(); e < span * pw; e += NTHR) {
+        const int rr = e % span, c = e / span;
+        const int cc = c0 + c;
+        const int sb = ib <= P ? (cc / ib) * ib : sg;  // block start of column cc
+        const int ra = rlo + rr;                       // row within T_s
+        const int rc = cc - sb;                        // column within T_s
+        if (ra < min(ib, K - sb)) {
+          const int la = ra - rlo + (ib <= P ? sb - c0 : 0);  // local row in tg
+          Tg[ra + (int64_t)cc * ib] = ra <= rc ? (double)L.tg[la * ld + c] : 0.0;
+        }
+      }
+    }
+    __syncthreads();
+    // --- the rest of the tile: trailing columns [c0 + pw, ncol) ---
+    const int rest = ncol - c0 - pw;
+    if (rest > 0) {
+      const double *Vp = ts ? X + (int64_t)c0 * lda : X + c0 + (int64_t)c0 * lda;
+      const int vrows = ts ? mrows : mrows - c0;
+      double *C1 = ts ? R + c0 + (int64_t)(c0 + pw) * lda : nullptr;
+      double *C2 = ts ? X + (int64_t)(c0 + pw) * lda : X + c0 + (int64_t)(c0 + pw) * lda;
+      const double *Ta = ib <= P ? Tp + (int64_t)c0 * ib : Tp + (c0 - sg) + (int64_t)c0 * ib;
+      apply_cols<RW>(L, Vp, lda, vrows, ts ? VK_FULL : VK_UNIT, pw, ib <= P ? ib : pw, Ta, ib, C1, lda,
+                 C2, lda, rest);
     }
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < m0 * pw; e += NTHR) {
-    const int a = e % m0, c = e / m0;
-    double acc = 0.0;
-    for (int b = a; b < m0; ++b) acc += Tg[a + (int64_t)b * ldt] * G[b * 16 + c];
-    Tg[a + (int64_t)(m0 + c) * ldt] = -acc;
+  if (ib > P) {
+    for (int sg = 0; sg < K; sg += ib) {
+      const int bw = min(ib, K - sg);
+      if (bw <= P) continue;
+      const double *Vb = ts ? X + (int64_t)sg * lda : X + sg + (int64_t)sg * lda;
+      assemble_wide_T<RW>(L, Vb, lda, ts ? mrows : mrows - sg, ts ? VK_FULL : VK_UNIT, bw,
+                      Tp + (int64_t)sg * ib, ib);
+    }
   }
-  for (int e = threadIdx.x; e < m0 * pw; e += NTHR) {
-    const int a = e % pw, c = e / pw;
-    Tg[(m0 + a) + (int64_t)c * ldt] = 0.0;
-  }
-  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
 // Task dispatch and the persistent scheduler
 // ---------------------------------------------------------------------------
 
-
-// Runs one task. Every task is a sequence of steps that end with one
-// block-reflector application; panels precede it with the factorization of
-// a micro-panel. A single call site of the MFMA routine (and of the panel
-// routine) keeps the register allocation of the fused kernel tight.
-template <int MBT>
+template <int RW>
 __device__ __forceinline__ void run_task(const Task &t, const MatDesc &m, const Lds &L) {
-  constexpr int HRW = (MBT * 16 + 63) / 64;  // panel rows per lane of the panel wave
-  constexpr int PWV = HRW >= 2 ? 8 : 16;     // micro-panel width held in registers
-  const int nb = m.nb, ib = m.ib, nw = m.w >> 4;
+  const int nb = m.nb, ib = m.ib;
   const int i = t.i, j = t.j, k = t.k, strip = task_strip(t);
   const int type = task_type(t);
-  auto At = [&](int r, int c) { return m.A + (int64_t)c * nb * m.lda + (int64_t)r * nb; };
-  auto Tt = [&](int r, int c) { return m.T + ((int64_t)c * m.MT + r) * (int64_t)ib * nb; };
-  const int64_t lda = m.lda;
-  const bool panel = type == TK_GEQRT || type == TK_TSQRT;
-  const bool ts = type == TK_TSQRT;
-
-  // Panel state (GEQRT: factor A_kk; TSQRT: factor [R_kk; A_ik]).
-  double *R = At(k, k);
-  double *U = ts ? At(i, k) : R;
-  double *Tp = ts ? Tt(i, k) : Tt(k, k);
-  const int pmb = ts ? tile_rows(m, i) : tile_rows(m, k);
-  const int pcol = tile_cols(m, k);
-  const int K = ts ? pcol : min(pmb, pcol);
-  int s = 0, m0 = 0;
-  if (panel) {
+  if (type == TK_GEQRT || type == TK_TSQRT) {
     // Panels are the critical path: their waves win instruction issue over
     // co-resident update waves.
     __builtin_amdgcn_s_setprio(2);
+    panel_task<RW>(m, L, type == TK_TSQRT, i, k);
+    __builtin_amdgcn_s_setprio(0);
+    return;
   }
-
-  // Panel steps: factor a micro-panel, then (if it is not the first of its
-  // IB block) the Gram product of the T assembly, then the update of the
-  // rest of the block or, after the block's last micro-panel, of the
-  // trailing columns. Each loop iteration makes exactly one application.
-  int phase = 0;  // 0: factor next micro-panel, 1: T assembly done -> update
-  int pw = 0;
-  for (;;) {
-    const double *aV, *aT;
-    double *aC1, *aC2;
-    int64_t ldc1 = lda, ldc2 = lda;
-    int vrows, kind, kref, aib, ncols, c2diag = 0;
-    bool go = true, yonly = false, post_asm = false;
-    if (panel) {
-      if (s >= K) break;
-      const int ibw = min(ib, K - s);
-      // Block frame: GEQRT rows/cols start at s; TSQRT rows of U start at 0.
-      double *Xb = ts ? U + (int64_t)s * lda : U + s + (int64_t)s * lda;
-      double *Rb = R + s + (int64_t)s * lda;
-      double *Tb = Tp + (int64_t)s * ib;
-      const int mrows = ts ? pmb : pmb - s;
-      kind = ts ? VK_FULL : VK_UNIT;
-      if (phase == 0) {
-        pw = min(PWV, ibw - m0);
-        if (ts) {
-          const gdbl *Rg = gp(Rb);
-          for (int e = threadIdx.x; e < 32 * 32; e += NTHR) {
-            const int a = e >> 5, c = e & 31;
-            L.top[a * 33 + c] = (a <= c && c < pw) ? Rg[(m0 + a) + (int64_t)(m0 + c) * lda] : 0.0;
-          }
-          __syncthreads();
-        }
-        level2_panel<HRW, PWV>(L, ts, Xb, lda, mrows, m0, pw, Tb + m0 + (int64_t)m0 * ib, ib);
-        if (ts) {
-          gdbl *Rg = gp(Rb);
-          for (int e = threadIdx.x; e < 32 * 32; e += NTHR) {
-            const int a = e >> 5, c = e & 31;
-            if (a <= c && c < pw) Rg[(m0 + a) + (int64_t)(m0 + c) * lda] = L.top[a * 33 + c];
-          }
-          __syncthreads();
-        }
-      }
-      if (phase == 0 && m0 > 0) {
-        // Gram block V[:, 0:m0]^T V[:, m0:m0+pw] (Y of a one-block application)
-        aV = Xb;
-        vrows = mrows;
-        kref = m0;
-        aib = m0;
-        aT = Tb;
-        aC1 = nullptr;
-        aC2 = Xb + (int64_t)m0 * lda;
-        ncols = pw;
-        yonly = true;
-        post_asm = true;
-        c2diag = ts ? -1 : m0;  // GEQRT vectors: unit at row m0 + col
-        phase = 1;
-      } else if (m0 + pw < ibw) {
-        // this micro-panel's reflectors onto the rest of the IB block
-        aV = ts ? Xb + (int64_t)m0 * lda : Xb + m0 + (int64_t)m0 * lda;
-        vrows = ts ? mrows : mrows - m0;
-        kref = pw;
-        aib = pw;
-        aT = Tb + m0 + (int64_t)m0 * ib;
-        aC1 = ts ? Rb + m0 + (int64_t)(m0 + pw) * lda : nullptr;
-        aC2 = ts ? Xb + (int64_t)(m0 + pw) * lda : Xb + m0 + (int64_t)(m0 + pw) * lda;
-        ncols = ibw - m0 - pw;
-        m0 += pw;
-        phase = 0;
-      } else {
-        // the whole IB block onto the trailing columns of the tile
-        aV = Xb;
-        vrows = mrows;
-        kref = ibw;
-        aib = ibw;
-        aT = Tb;
-        aC1 = ts ? Rb + (int64_t)ibw * lda : nullptr;
-        aC2 = Xb + (int64_t)ibw * lda;
-        ncols = pcol - s - ibw;
-        go = ncols > 0;
-        s += ibw;
-        m0 = 0;
-        phase = 0;
-      }
+  auto At = [&](int r, int c) { return m.A + (int64_t)c * nb * m.lda + (int64_t)r * nb; };
+  auto Tt = [&](int r, int c) { return m.T + ((int64_t)c * m.MT + r) * (int64_t)ib * nb; };
+  const int64_t lda = m.lda;
+  const int c0 = strip * m.w;
+  const bool onB = type == TK_LARFB_B || type == TK_SSRFB_B;
+  const bool larfb = type == TK_LARFB || type == TK_LARFB_B;
+  const double *aV, *aT;
+  int vrows, kind, kref;
+  if (larfb) {
+    const int mb = tile_rows(m, k);
+    aV = At(k, k);
+    vrows = mb;
+    kind = VK_UNIT;
+    kref = min(mb, tile_cols(m, k));
+    aT = Tt(k, k);
+  } else {
+    aV = At(i, k);
+    vrows = tile_rows(m, i);
+    kind = VK_FULL;
+    kref = tile_cols(m, k);
+    aT = Tt(i, k);
+  }
+  double *aC1 = nullptr, *aC2;
+  int64_t ldc = lda;
+  int ncols;
+  if (onB) {
+    ncols = min(m.w, m.nrhs - c0);
+    ldc = m.ldb;
+    double *Bk = m.B + (int64_t)k * nb + (int64_t)c0 * m.ldb;
+    if (larfb) {
+      aC2 = Bk;
     } else {
-      aib = ib;
-      aC1 = nullptr;
-      const int c0 = strip * m.w;
-      const bool onB = type == TK_LARFB_B || type == TK_SSRFB_B;
-      const bool larfb = type == TK_LARFB || type == TK_LARFB_B;
-      if (larfb) {
-        const int mb = tile_rows(m, k);
-        aV = At(k, k);
-        vrows = mb;
-        kind = VK_UNIT;
-        kref = min(mb, tile_cols(m, k));
-        aT = Tt(k, k);
-      } else {
-        aV = At(i, k);
-        vrows = tile_rows(m, i);
-        kind = VK_FULL;
-        kref = tile_cols(m, k);
-        aT = Tt(i, k);
-      }
-      if (onB) {
-        ncols = min(m.w, m.nrhs - c0);
-        ldc1 = ldc2 = m.ldb;
-        double *Bk = m.B + (int64_t)k * nb + (int64_t)c0 * m.ldb;
-        if (larfb) {
-          aC2 = Bk;
-        } else {
-          aC1 = Bk;
-          aC2 = m.B + (int64_t)i * nb + (int64_t)c0 * m.ldb;
-        }
-      } else {
-        ncols = min(m.w, tile_cols(m, j) - c0);
-        if (larfb) {
-          aC2 = At(k, j) + (int64_t)c0 * lda;
-        } else {
-          aC1 = At(k, j) + (int64_t)c0 * lda;
-          aC2 = At(i, j) + (int64_t)c0 * lda;
-        }
-      }
+      aC1 = Bk;
+      aC2 = m.B + (int64_t)i * nb + (int64_t)c0 * m.ldb;
     }
-    if (go)
-      apply_cols<MBT>(L, aV, lda, vrows, kind, kref, aib, aT, ib, aC1, ldc1, aC2, ldc2, ncols, nw,
-                      yonly, c2diag);
-    if (post_asm) assemble_T_post(L, m0, pw, Tp + (int64_t)s * ib, ib);
-    if (!panel) break;
+  } else {
+    ncols = min(m.w, tile_cols(m, j) - c0);
+    if (larfb) {
+      aC2 = At(k, j) + (int64_t)c0 * lda;
+    } else {
+      aC1 = At(k, j) + (int64_t)c0 * lda;
+      aC2 = At(i, j) + (int64_t)c0 * lda;
+    }
   }
-  if (panel) __builtin_amdgcn_s_setprio(0);
+  apply_cols<RW>(L, aV, lda, vrows, kind, kref, ib, aT, ib, aC1, ldc, aC2, ldc, ncols);
+}
+
+// The task's matrix descriptor, field by field from the batch array or the
+// kernel argument (a whole-struct select between the two would give the
+// descriptor an address and a private-memory copy).
+__device__ __forceinline__ MatDesc load_desc(const MatDesc *__restrict__ mats, int idx,
+                                             const MatDesc &single) {
+  if (!mats) return single;
+  const MatDesc *g = mats + idx;
+  MatDesc m;
+  m.A = g->A;
+  m.T = g->T;
+  m.B = g->B;
+  m.lda = g->lda;
+  m.ldb = g->ldb;
+  m.ctr = g->ctr;
+  m.M = g->M;
+  m.N = g->N;
+  m.nb = g->nb;
+  m.ib = g->ib;
+  m.MT = g->MT;
+  m.NT = g->NT;
+  m.KT = g->KT;
+  m.S = g->S;
+  m.w = g->w;
+  m.nrhs = g->nrhs;
+  m.SB = g->SB;
+  m.gmax = g->gmax;
+  return m;
 }
 
 __device__ inline int ld_acquire(const int *p) {
@@ -799,7 +998,7 @@ __device__ inline int ld_acquire(const int *p) {
 // Thread 0 polls the task's counters; gives up (and flags `err`) after
 // `timeout` wall-clock ticks or when another workgroup flagged an error.
 __device__ __forceinline__ bool wait_deps(const Task &t, const MatDesc &m, const int *ctr, int *err,
-                          long long timeout) {
+                                          long long timeout) {
   __shared__ int s_ok;
   if (threadIdx.x == 0) {
     int ok = 1;
@@ -833,13 +1032,10 @@ __device__ __forceinline__ bool wait_deps(const Task &t, const MatDesc &m, const
   return ok != 0;
 }
 
-template <int MBT>
-__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(MBT <= TQ_WPE2_MAX_MBT ? 2 : 1, MBT <= TQ_WPE2_MAX_MBT ? 2 : 1))) void tq_persistent(const Task *__restrict__ tasks,
-                                                      int64_t ntasks, MatDesc single,
-                                                      const MatDesc *__restrict__ mats, int *ctr,
-                                                      unsigned int *ticket, int *err,
-                                                      int use_waits, long long timeout,
-                                                      long long *trace) {
+__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(2, 2))) void tq_persistent(
+    const Task *__restrict__ tasks, int64_t ntasks, MatDesc single,
+    const MatDesc *__restrict__ mats, int *ctr, unsigned int *ticket, int *err, int use_waits,
+    long long timeout, long long *trace) {
   extern __shared__ double lds_dyn[];
   __shared__ int s_t;
   for (;;) {
@@ -854,12 +1050,15 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(MBT <= TQ_
     __syncthreads();
     if (t < 0 || t >= ntasks) break;
     const Task tk = tasks[t];
-    const MatDesc m = mats ? mats[task_mat(tk)] : single;
+    const MatDesc m = load_desc(mats, task_mat(tk), single);
     const long long t_take = trace ? wall_clock64() : 0;
     if (use_waits && !wait_deps(tk, m, ctr, err, timeout)) break;
     const long long t_run = trace ? wall_clock64() : 0;
-    const Lds L = make_lds(lds_dyn, MBT, m.ib, m.w >> 4, m.gmax);
-    run_task<MBT>(tk, m, L);
+    switch (m.w) {
+      case 64: run_task<1>(tk, m, make_lds<1>(lds_dyn, m)); break;
+      case 32: run_task<2>(tk, m, make_lds<2>(lds_dyn, m)); break;
+      default: run_task<4>(tk, m, make_lds<4>(lds_dyn, m)); break;
+    }
     __threadfence();
     __syncthreads();
     if (trace && threadIdx.x == 0) {
@@ -885,16 +1084,26 @@ __global__ void tq_zero_ints(int *p, int64_t n) {
 
 // Step-1 kernel benchmark: every workgroup applies `calls` full-tile SSRFBs
 // (all strips) to its own tiles, one after the other.
-template <int MBT>
-__global__ __launch_bounds__(NTHR) void tq_ssrfb_bench(double *buf, int nb, int ib, int calls,
-                                                       int nw) {
+__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(2, 2))) void tq_ssrfb_bench(
+    double *buf, MatDesc m, int calls) {
   extern __shared__ double lds_dyn[];
-  const Lds L = make_lds(lds_dyn, MBT, ib, nw, lds_plan(MBT, ib).gmax);
+  const int nb = m.nb, ib = m.ib;
   const int64_t per = 3 * (int64_t)nb * nb + (int64_t)ib * nb;
   double *V = buf + per * blockIdx.x;
   double *C1 = V + (int64_t)nb * nb, *C2 = C1 + (int64_t)nb * nb, *T = C2 + (int64_t)nb * nb;
-  for (int call = 0; call < calls; ++call)
-    apply_cols<MBT>(L, V, nb, nb, VK_FULL, nb, ib, T, ib, C1, nb, C2, nb, nb, nw, false, 0);
+  for (int call = 0; call < calls; ++call) {
+    switch (m.w) {
+      case 64:
+        apply_cols<1>(make_lds<1>(lds_dyn, m), V, nb, nb, VK_FULL, nb, ib, T, ib, C1, nb, C2, nb, nb);
+        break;
+      case 32:
+        apply_cols<2>(make_lds<2>(lds_dyn, m), V, nb, nb, VK_FULL, nb, ib, T, ib, C1, nb, C2, nb, nb);
+        break;
+      default:
+        apply_cols<4>(make_lds<4>(lds_dyn, m), V, nb, nb, VK_FULL, nb, ib, T, ib, C1, nb, C2, nb, nb);
+        break;
+    }
+  }
 }
 
 // Deterministic fill with values in [-scale, scale] (splitmix64 hash).
@@ -909,39 +1118,10 @@ __global__ void tq_fill_hash(double *p, int64_t n, uint64_t seed, double scale) 
   }
 }
 
-template <int MBT>
-hipError_t launch_persistent_t(const TqLaunch &a, hipStream_t st) {
-  auto kern = tq_persistent<MBT>;
-  if (a.lds_bytes > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)a.lds_bytes);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(kern, dim3(a.grid), dim3(NTHR), a.lds_bytes, st, a.tasks, a.ntasks, a.single,
-                     a.mats, a.ctr, a.ticket, a.err, a.use_waits, a.timeout, a.trace);
-  return hipGetLastError();
-}
-
-template <int MBT>
-int occupancy_t(size_t lds) {
-  auto kern = tq_persistent<MBT>;
+hipError_t set_lds(const void *kern, size_t lds) {
   if (lds > 64 * 1024)
-    hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  int nblk = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, kern, NTHR, lds) != hipSuccess) return 1;
-  return nblk > 0 ? nblk : 1;
-}
-
-template <int MBT>
-hipError_t launch_bench_t(double *buf, int nb, int ib, int calls, int nw, int grid, hipStream_t st) {
-  auto kern = tq_ssrfb_bench<MBT>;
-  size_t lds = (size_t)lds_plan(MBT, ib).doubles * 8;
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(NTHR), lds, st, buf, nb, ib, calls, nw);
-  return hipGetLastError();
+    return hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  return hipSuccess;
 }
 
 }  // namespace
@@ -953,34 +1133,35 @@ hipError_t tq_launch_persistent(const TqLaunch &a, hipStream_t st) {
     g = g > 1024 ? 1024 : (g < 1 ? 1 : g);
     hipLaunchKernelGGL(tq_zero_ints, dim3(g), dim3(256), 0, st, a.ctr_base, n);
   }
-  switch (a.mbt) {
-    case 4: return launch_persistent_t<4>(a, st);
-    case 8: return launch_persistent_t<8>(a, st);
-    case 16: return launch_persistent_t<16>(a, st);
-    case 32: return launch_persistent_t<32>(a, st);
-  }
-  return hipErrorInvalidValue;
+  hipError_t e = set_lds((const void *)tq_persistent, a.lds_bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(tq_persistent, dim3(a.grid), dim3(NTHR), a.lds_bytes, st, a.tasks, a.ntasks,
+                     a.single, a.mats, a.ctr, a.ticket, a.err, a.use_waits, a.timeout, a.trace);
+  return hipGetLastError();
 }
 
-int tq_occupancy(int mbt, size_t lds) {
-  switch (mbt) {
-    case 4: return occupancy_t<4>(lds);
-    case 8: return occupancy_t<8>(lds);
-    case 16: return occupancy_t<16>(lds);
-    case 32: return occupancy_t<32>(lds);
-  }
-  return 1;
+int tq_occupancy(size_t lds) {
+  if (set_lds((const void *)tq_persistent, lds) != hipSuccess) return 1;
+  int nblk = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, tq_persistent, NTHR, lds) != hipSuccess)
+    return 1;
+  return nblk > 0 ? nblk : 1;
 }
 
 hipError_t tq_launch_ssrfb_bench(double *buf, int nb, int ib, int calls, int grid, hipStream_t st) {
-  const int nw = nwaves_for(nb, ib);
-  switch (mbt_for_nb(nb)) {
-    case 4: return launch_bench_t<4>(buf, nb, ib, calls, nw, grid, st);
-    case 8: return launch_bench_t<8>(buf, nb, ib, calls, nw, grid, st);
-    case 16: return launch_bench_t<16>(buf, nb, ib, calls, nw, grid, st);
-    case 32: return launch_bench_t<32>(buf, nb, ib, calls, nw, grid, st);
-  }
-  return hipErrorInvalidValue;
+  const LdsPlan lp = lds_plan(nb, ib);
+  if (lp.gmax < 1) return hipErrorInvalidValue;
+  MatDesc m;
+  __builtin_memset(&m, 0, sizeof(m));
+  m.nb = nb;
+  m.ib = ib;
+  m.w = strip_width(nb);
+  m.gmax = lp.gmax;
+  const size_t lds = (size_t)lp.doubles * 8;
+  hipError_t e = set_lds((const void *)tq_ssrfb_bench, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(tq_ssrfb_bench, dim3(grid), dim3(NTHR), lds, st, buf, m, calls);
+  return hipGetLastError();
 }
 
 hipError_t tq_launch_fill(double *p, int64_t n, uint64_t seed, double scale, hipStream_t st) {

@@ -29,6 +29,7 @@ def build(out_dir):
     s = s.replace("extern __shared__ double lds_dyn[];", "double *lds_dyn = g_dyn_lds;")
     s = re.sub(r"__attribute__\(\(amdgpu_waves_per_eu\([^)]*\)\)\)", "", s)
     s = s.replace("typedef double d4 __attribute__((ext_vector_type(4)));", "typedef emu_d4 d4;")
+    s = s.replace('asm volatile("" : "+v"(t));', "")
     dev = os.path.join(out_dir, "device_emu.cpp")
     open(dev, "w").write(s)
     m = open(os.path.join(CSRC, "tileqr_mlp.hip")).read()

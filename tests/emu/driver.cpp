@@ -14,13 +14,10 @@ extern "C" {
 void oracle_geqr2(int64_t m, int64_t n, double *a, int64_t lda, double *tau);
 void oracle_apply_qt(int64_t m, int64_t k, const double *v, int64_t ldv, const double *tau, int64_t nrhs, double *b, int64_t ldb);
 }
-static int nw_for(int mbt, int ib) { return lds_plan(mbt, ib).nw; }
 
 static int run(std::vector<MatDesc> mats, bool apply, int grid) {
-  int mbt = 4;
-  for (auto &m : mats) mbt = std::max(mbt, mbt_for_nb(m.nb));
   size_t lds = 0; int64_t c = 0;
-  for (auto &m : mats) { m.ctr = c; c += apply ? ctr_count_apply(m) : ctr_count_factor(m); lds = std::max(lds, (size_t)lds_plan(mbt, m.ib).doubles * 8); }
+  for (auto &m : mats) { m.ctr = c; c += apply ? ctr_count_apply(m) : ctr_count_factor(m); lds = std::max(lds, (size_t)lds_plan(m.nb, m.ib).doubles * 8); }
   std::vector<Task> order; int64_t nctr = 0;
   if (build_order(mats, apply, grid, order, &nctr)) { printf("build_order failed\n"); return 1; }
   std::vector<int> ctr(nctr + 64, 0);
@@ -29,7 +26,7 @@ static int run(std::vector<MatDesc> mats, bool apply, int grid) {
   TqLaunch a;
   a.tasks = order.data(); a.ntasks = order.size(); a.single = mats[0]; a.mats = mats.size() > 1 ? dm.data() : nullptr;
   a.ctr = ctr.data(); a.ctr_base = ctr.data(); a.nctr_zero = nctr + 1; a.ticket = (unsigned *)(ctr.data() + nctr);
-  a.trace = nullptr; a.err = &err; a.use_waits = 1; a.timeout = 1LL << 60; a.lds_bytes = lds; a.grid = grid; a.mbt = mbt;
+  a.trace = nullptr; a.err = &err; a.use_waits = 1; a.timeout = 1LL << 60; a.lds_bytes = lds; a.grid = grid;
   tq_launch_persistent(a, nullptr);
   if (err) printf("device error %d\n", err);
   return err;
@@ -42,12 +39,10 @@ static int batch_main(int count, int seed) {
   std::uniform_real_distribution<double> U(-1, 1);
   const int nbs[3] = {64, 96, 128}, ibs[3][3] = {{16, 32, 64}, {16, 24, 48}, {16, 32, 128}};
   std::vector<int> Ms, Ns, NBs, IBs;
-  int mbt = 4;
   for (int b = 0; b < count; ++b) {
     int M = 40 + (int)(g() % 150), N = 20 + (int)(g() % M);
     int c = (int)(g() % 3);
     Ms.push_back(M); Ns.push_back(N); NBs.push_back(nbs[c]); IBs.push_back(ibs[c][g() % 3]);
-    mbt = std::max(mbt, mbt_for_nb(nbs[c]));
   }
   std::vector<std::vector<double>> As(count), A0s(count), Ts(count);
   std::vector<MatDesc> mats;
@@ -57,8 +52,8 @@ static int batch_main(int count, int seed) {
     for (auto &x : As[b]) x = U(g);
     A0s[b] = As[b];
     MatDesc md; memset(&md, 0, sizeof md);
-    LdsPlan lp = lds_plan(mbt, ib);
-    md_init(md, M, N, nb, ib, 16 * lp.nw, M);
+    LdsPlan lp = lds_plan(nb, ib);
+    md_init(md, M, N, nb, ib, strip_width(nb), M);
     md.gmax = lp.gmax;
     md.lda = M;
     Ts[b].assign((size_t)md.KT * md.MT * ib * nb + 1, std::nan(""));
@@ -94,9 +89,8 @@ int main(int argc, char **argv) {
   for (auto &x : A) x = U(g);
   A0 = A; Ao = A;
   MatDesc md; memset(&md, 0, sizeof md);
-  int nw = nw_for(mbt_for_nb(nb), ib);
-  md_init(md, M, N, nb, ib, 16 * nw, M);
-  md.gmax = lds_plan(mbt_for_nb(nb), ib).gmax;
+  md_init(md, M, N, nb, ib, strip_width(nb), M);
+  md.gmax = lds_plan(nb, ib).gmax;
   md.lda = lda;
   std::vector<double> T((size_t)md.KT * md.MT * ib * nb + 1, std::nan(""));
   md.A = A.data(); md.T = T.data();

@@ -56,6 +56,7 @@ extern size_t g_dyn_lds_bytes;
 
 inline void __syncthreads() { std::atomic_thread_fence(std::memory_order_seq_cst); g_block_bar->arrive_and_wait(); }
 inline void __threadfence() { std::atomic_thread_fence(std::memory_order_seq_cst); }
+inline void __threadfence_block() { std::atomic_thread_fence(std::memory_order_seq_cst); }
 inline long long wall_clock64() { return 0; }
 inline void __builtin_amdgcn_s_sleep(int) { std::this_thread::yield(); }
 

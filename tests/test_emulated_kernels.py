@@ -2,9 +2,11 @@
 emulation in tests/emu (every lane a host thread, LDS laid out as on the
 device, MFMA with the measured gfx950 lane layout) with AddressSanitizer:
 the index arithmetic of every task kind stays in bounds, and the results
-match the oracle. Covers the tile classes NB <= 64 and NB <= 128, ragged
-tiles, odd inner blocks, the batched union DAG and the MLP kernels. Runs on
-the CPU; slow (about three minutes in all)."""
+match the oracle. Covers every row-wave class (NB <= 128: one wave per
+128-row slab of a column group; NB <= 256: two; NB <= 512: four), ragged
+tiles, inner blocks that do not divide NB, inner blocks wider than a
+register panel (the T assembly across panels), the batched union DAG and
+the MLP kernels. Runs on the CPU; slow (a few minutes in all)."""
 import os
 import subprocess
 import sys
@@ -33,9 +35,13 @@ def _run(args, timeout=600):
 
 
 @pytest.mark.parametrize("M,N,nb,ib", [
-    (97, 130, 64, 12),     # NB <= 64 class; wide, odd leading dimension, IB does not divide NB
-    (200, 150, 128, 32),   # NB <= 128 class, ragged both ways
-    (110, 100, 96, 96),    # NB = 96, IB = NB
+    (97, 130, 64, 12),     # wide, IB does not divide NB
+    (200, 150, 128, 32),   # ragged both ways
+    (110, 100, 96, 96),    # IB = NB wider than the 64-column register panel
+    (260, 120, 128, 128),  # three tile rows, IB = NB = 128
+    (150, 150, 136, 16),   # two row waves: LARFB/SSRFB with the register prefetch
+    (280, 40, 256, 48),    # two row waves, T assembled over two register panels
+    (520, 40, 512, 32),    # four row waves, T assembled over 16-column panels
 ])
 def test_tile_qr_emulated(emu, M, N, nb, ib):
     out = _run([emu[0], str(M), str(N), str(nb), str(ib)])
