@@ -291,6 +291,7 @@ __device__ inline int first_rt(int kind, int s, int q, int rbase) {
 // Y[q] (+)= V[:, s+16q ..]^T C2 over the wave's rows, into the group region
 // yw. The B operand is accumulator register r of C2 tile rt (k index
 // lane/16 <-> row 16*rt + 4*r + lane/16); the A operand is V^T at those rows.
+// Four independent accumulator chains (one per register r), summed at the end.
 template <int RW>
 __device__ inline void y_group(const Lds &L, int kind, int s, int q0, int ng, int vrows,
                                const d4 (&c2)[RT], ldbl *yw, int rbase, bool acc) {
@@ -298,31 +299,33 @@ __device__ inline void y_group(const Lds &L, int kind, int s, int q0, int ng, in
   const int ln = lane_id();
   for (int g = 0; g < ng; ++g) {
     const int q = q0 + g;
-    d4 y0 = {0.0, 0.0, 0.0, 0.0}, y1 = {0.0, 0.0, 0.0, 0.0};
+    d4 y[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) y[r] = d4{0.0, 0.0, 0.0, 0.0};
     const int rt0 = first_rt(kind, s, q, rbase);
     const ldbl *vp = L.vc + (g * 16 + (ln & 15)) * LDVC + rbase + (ln >> 4);
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
       if (rt >= rt0 && rbase + rt * 16 < vrows) {
-        y0 = mfma(vp[rt * 16 + 0], c2[rt][0], y0);
-        y1 = mfma(vp[rt * 16 + 4], c2[rt][1], y1);
-        y0 = mfma(vp[rt * 16 + 8], c2[rt][2], y0);
-        y1 = mfma(vp[rt * 16 + 12], c2[rt][3], y1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) y[r] = mfma(vp[rt * 16 + 4 * r], c2[rt][r], y[r]);
       }
     }
+    const d4 ys = (y[0] + y[1]) + (y[2] + y[3]);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       ldbl *d = yw + (q * 16 + 4 * r + (ln >> 4)) * 16 + (ln & 15);
       if (acc)
-        *d += y0[r] + y1[r];
+        *d += ys[r];
       else
-        *d = y0[r] + y1[r];
+        *d = ys[r];
     }
   }
 }
 
-// C2 -= V_s W over the wave's rows for the staged chunks: A = -V[row 16*rt +
-// lane%16][col 4kk + lane/16 of chunk q], B = W[16q + 4kk + lane/16][lane%16].
+// C2 -= V_s W over the wave's rows for the staged chunks: A = V[row 16*rt +
+// lane%16][col 4kk + lane/16 of chunk q], B = -W[16q + 4kk + lane/16][lane%16].
+// The row tiles are the independent accumulator chains (kk outermost).
 template <int RW>
 __device__ inline void update_group(const Lds &L, int kind, int s, int q0, int ng, int vrows,
                                     const ldbl *yw, d4 (&c2)[RT], int rbase) {
@@ -333,13 +336,14 @@ __device__ inline void update_group(const Lds &L, int kind, int s, int q0, int n
     const int rt0 = first_rt(kind, s, q, rbase);
     double b[4];
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) b[kk] = yw[(q * 16 + 4 * kk + (ln >> 4)) * 16 + (ln & 15)];
+    for (int kk = 0; kk < 4; ++kk) b[kk] = -yw[(q * 16 + 4 * kk + (ln >> 4)) * 16 + (ln & 15)];
     const ldbl *vp = L.vc + (g * 16 + (ln >> 4)) * LDVC + rbase + (ln & 15);
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-      if (rt >= rt0 && rbase + rt * 16 < vrows) {
+    for (int kk = 0; kk < 4; ++kk) {
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) c2[rt] = mfma(-vp[4 * kk * LDVC + rt * 16], b[kk], c2[rt]);
+      for (int rt = 0; rt < RT; ++rt) {
+        if (rt >= rt0 && rbase + rt * 16 < vrows)
+          c2[rt] = mfma(vp[4 * kk * LDVC + rt * 16], b[kk], c2[rt]);
       }
     }
   }
@@ -683,17 +687,33 @@ __device__ inline void t_column(const Lds &L, int cc, int tb) {
   const int a = lane_id();
   const double tau = L.taus[cc];
   if (a >= tb && a < cc) {
-    double t0 = 0.0, t1 = 0.0;
+    const ldbl *tr = L.tg + a * ld, *gr = L.tg + cc * ld;
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
     int p = a;
-    for (; p + 1 < cc; p += 2) {
-      t0 += L.tg[a * ld + p] * L.tg[cc * ld + p];
-      t1 += L.tg[a * ld + p + 1] * L.tg[cc * ld + p + 1];
+    for (; p + 3 < cc; p += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) t[u] += tr[p + u] * gr[p + u];
     }
-    if (p < cc) t0 += L.tg[a * ld + p] * L.tg[cc * ld + p];
-    L.tg[a * ld + cc] = -tau * (t0 + t1);
+    for (; p < cc; ++p) t[0] += tr[p] * gr[p];
+    L.tg[a * ld + cc] = -tau * ((t[0] + t[1]) + (t[2] + t[3]));
   }
   if (a == cc) L.tg[cc * ld + cc] = tau;
   wave_sync();
+}
+
+// The T blocks of a register panel of pw columns, from the Gram entries and
+// tau in LDS: blocks of ib columns (one per wave, round robin) when IB <= P,
+// else the panel's own diagonal block.
+template <int RW>
+__device__ inline void panel_T(const Lds &L, int pw, int ib) {
+  constexpr int P = Geo<RW>::P;
+  const int wv = wave_id();
+  const int bw = ib <= P ? ib : pw;
+  const int nblk = (pw + bw - 1) / bw;
+  for (int b = wv; b < nblk; b += 4) {
+    const int tb = b * bw, te = min(tb + bw, pw);
+    for (int cc = tb; cc < te; ++cc) t_column<RW>(L, cc, tb);
+  }
 }
 
 // GEQRT(k) (ts = false): QR of the diagonal tile in place.
@@ -836,11 +856,9 @@ __device__ __forceinline__ void panel_task(const MatDesc &m, const Lds &L, bool 
       // Gram entry G[mc][c] of two reflectors of the same T block
       const int tbc = ib <= P ? (j / ib) * ib - c0 : 0;
       if (mc < c && mc >= tbc && g4 == 0 && rb == 0) L.tg[c * ld + mc] = d;
-      // T column c-1, one column behind the factorization
-      if (wv == 0 && c > 0) t_column<RW>(L, c - 1, ib <= P ? ((j - 1) / ib) * ib - c0 : 0);
     }
     __syncthreads();
-    if (wv == 0) t_column<RW>(L, pw - 1, ib <= P ? ((c0 + pw - 1) / ib) * ib - c0 : 0);
+    panel_T<RW>(L, pw, ib);
     // --- write back the panel: R above, reflectors below ---
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
