@@ -84,11 +84,21 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Sum over the four lanes that hold the rows of one column (l, l^16, l^32,
-// l^48); every one of them gets the total.
-__device__ inline double col_sum(double v) {
-  v += __shfl_xor(v, 16);
-  v += __shfl_xor(v, 32);
+// A double from lane l ^ 1 (CTRL = 0xB1, quad_perm [1,0,3,2]) or l ^ 2
+// (CTRL = 0x4E, quad_perm [2,3,0,1]) by DPP: a register move, no LDS trip.
+template <int CTRL>
+__device__ __forceinline__ double dpp_quad(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum over the four adjacent lanes of a quad (the lanes holding the rows of
+// one column in the panel layout); every one of them gets the total.
+__device__ inline double quad_sum(double v) {
+  v += dpp_quad<0xB1>(v);
+  v += dpp_quad<0x4E>(v);
   return v;
 }
 
@@ -160,7 +170,23 @@ __device__ inline void vstage_load(double (&v)[PF], const double *V, int64_t ldv
   const int tid = tid_x();
   const int e0 = ebase + tid;
   const int r0 = e0 % ROWS, c0 = gc0 + e0 / ROWS;
-  const gdbl *Vb = gp(V) + (int64_t)c0 * ldv + r0;
+  const gdbl *Vg = gp(V);
+  // uniform: every element below `total` lies inside the block (total is a
+  // multiple of 256, so e < total is the uniform test ebase + 256u < total)
+  const int eend = min(total, ebase + PF * NTHR);
+  if (vrows == ROWS && gc0 + eend / ROWS <= kvalid) {
+    const gdbl *Vb = Vg + (int64_t)c0 * ldv + r0;
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      if (ebase + u * NTHR >= total) break;
+      const int du = ROWS <= NTHR ? u * CPU : u >> 1;
+      const int dr = ROWS <= NTHR ? 0 : (u & 1) * NTHR;
+      const double val = Vb[(int64_t)du * ldv + dr];
+      const int r = r0 + dr, gc = c0 + du;
+      v[u] = (kind == VK_UNIT) ? (r < gc ? 0.0 : (r == gc ? 1.0 : val)) : val;
+    }
+    return;
+  }
 #pragma unroll
   for (int u = 0; u < PF; ++u) {
     // ROWS = 512: u even -> rows r0, u odd -> rows r0 + 256 of the same column
@@ -168,12 +194,12 @@ __device__ inline void vstage_load(double (&v)[PF], const double *V, int64_t ldv
     const int dr = ROWS <= NTHR ? 0 : (u & 1) * NTHR;
     const int e = e0 + u * NTHR;
     const int r = r0 + dr, gc = c0 + du;
-    double x = 0.0;
-    if (e < total && r < vrows && gc < kvalid) {
-      const double val = Vb[(int64_t)du * ldv + dr];
-      x = (kind == VK_UNIT) ? (r < gc ? 0.0 : (r == gc ? 1.0 : val)) : val;
-    }
-    v[u] = x;
+    // always read an element of the block (clamped indices), then select:
+    // no branch per element
+    const double val = Vg[min(r, vrows - 1) + (int64_t)min(gc, kvalid - 1) * ldv];
+    const bool ok = e < total && r < vrows && gc < kvalid;
+    const double y = (kind == VK_UNIT) ? (r < gc ? 0.0 : (r == gc ? 1.0 : val)) : val;
+    v[u] = ok ? y : 0.0;
   }
 }
 
@@ -189,6 +215,16 @@ __device__ inline void vstage_store(const Lds &L, const double (&v)[PF], int vro
   const int e0 = ebase + tid_x();
   const int r0 = e0 % ROWS, c0 = e0 / ROWS;
   ldbl *lb = L.vc + c0 * LDVC + r0;
+  if (rlim == ROWS) {  // uniform: every row stored; e < total is uniform per u
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      if (ebase + u * NTHR >= total) break;
+      const int du = ROWS <= NTHR ? u * CPU : u >> 1;
+      const int dr = ROWS <= NTHR ? 0 : (u & 1) * NTHR;
+      lb[du * LDVC + dr] = v[u];
+    }
+    return;
+  }
 #pragma unroll
   for (int u = 0; u < PF; ++u) {
     const int du = ROWS <= NTHR ? u * CPU : u >> 1;
@@ -219,7 +255,8 @@ __device__ inline void tstage_load(double (&v)[TPF], const double *Tb, int64_t l
   for (int u = 0; u < TPF; ++u) {
     const int e = u * NTHR + tid_x();
     const int a = e / TQ_TS_MAX, c = e % TQ_TS_MAX;
-    v[u] = (a <= c && c < ibw) ? Tg[a + (int64_t)c * ldt] : 0.0;
+    const double val = Tg[min(a, ibw - 1) + (int64_t)min(c, ibw - 1) * ldt];
+    v[u] = (a <= c && c < ibw) ? val : 0.0;
   }
 }
 __device__ inline void tstage_store(const Lds &L, const double (&v)[TPF], int ibp) {
@@ -239,41 +276,66 @@ __device__ inline void c1_load(double (&v)[CPF], const double *C1, int64_t ldc1,
                                int ncols, int cg) {
   const int ln = lane_id();
   const int c = cg * 16 + (ln & 15);
-  const gdbl *Cb = gp(C1) + (int64_t)c * ldc1 + s + (ln >> 4);
+  const gdbl *Cb = gp(C1) + (int64_t)min(c, ncols - 1) * ldc1 + s;
 #pragma unroll
   for (int u = 0; u < CPF; ++u) {
     const int a = 4 * u + (ln >> 4);
-    v[u] = (a < ibw && c < ncols) ? Cb[4 * u] : 0.0;
+    const double val = Cb[min(a, ibw - 1)];
+    v[u] = (a < ibw && c < ncols) ? val : 0.0;
   }
 }
 
-// C[rbase + 0 .. 128) x column `col` into the accumulator layout.
+// C[rbase + 0 .. 128) x column `col` into registers: item (rt, r) of the
+// lane holds row 16*rt + 4*r + g, where g = lane/16 in the accumulator layout
+// of the MFMA (QUAD = false) and g = lane%4 in the panel layout (QUAD = true,
+// whose four lanes of a column are adjacent).
+template <bool QUAD = false>
 __device__ inline void load_c2(d4 (&c2)[RT], const double *C, int64_t ldc, int crows, int col,
                                bool colok, int rbase) {
-  const int g = lane_id() >> 4;
-  const gdbl *Cb = gp(C) + (int64_t)col * ldc + rbase + g;
+  // (crows >= 1, and col is clamped to a valid column when !colok)
+  const int g = QUAD ? (lane_id() & 3) : (lane_id() >> 4);
+  const gdbl *Cc = gp(C) + (int64_t)col * ldc;
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
+    const int lo = rbase + rt * 16;  // uniform
+    if (lo + 16 <= crows) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = rbase + rt * 16 + 4 * r + g;
-      c2[rt][r] = (colok && row < crows) ? Cb[rt * 16 + 4 * r] : 0.0;
+      for (int r = 0; r < 4; ++r) {
+        const double val = Cc[lo + 4 * r + g];
+        c2[rt][r] = colok ? val : 0.0;
+      }
+    } else if (lo < crows) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = lo + 4 * r + g;
+        const double val = Cc[min(row, crows - 1)];
+        c2[rt][r] = (colok && row < crows) ? val : 0.0;
+      }
+    } else {
+      c2[rt] = d4{0.0, 0.0, 0.0, 0.0};
     }
   }
 }
 
+template <bool QUAD = false>
 __device__ inline void store_c2(const d4 (&c2)[RT], double *C, int64_t ldc, int crows, int col,
                                 bool colok, int rbase) {
   if (!colok) return;
-  const int g = lane_id() >> 4;
-  gdbl *Cb = gp(C) + (int64_t)col * ldc + rbase + g;
+  const int g = QUAD ? (lane_id() & 3) : (lane_id() >> 4);
+  gdbl *Cc = gp(C) + (int64_t)col * ldc;
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
-    if (rbase + rt * 16 >= crows) break;
+    const int lo = rbase + rt * 16;  // uniform
+    if (lo >= crows) break;
+    if (lo + 16 <= crows) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = rbase + rt * 16 + 4 * r + g;
-      if (row < crows) Cb[rt * 16 + 4 * r] = c2[rt][r];
+      for (int r = 0; r < 4; ++r) Cc[lo + 4 * r + g] = c2[rt][r];
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = lo + 4 * r + g;
+        if (row < crows) Cc[row] = c2[rt][r];
+      }
     }
   }
 }
@@ -433,7 +495,7 @@ __device__ __forceinline__ void apply_strip(const Lds &L, const double *V, int64
   ldbl *yw = L.y + cg * L.ibp * 16;
   const bool c1w = C1 != nullptr && rb == 0 && gact;
   d4 c2[RT];
-  load_c2(c2, C2, ldc2, vrows, col, colok && gact, rbase);
+  load_c2(c2, C2, ldc2, vrows, min(col, ncols - 1), colok && gact, rbase);
   double pv[PF], pt[TPF], pc[CPF];
   if (pf) {
     const int ibw0 = min(ib, kref);
@@ -477,10 +539,15 @@ __device__ __forceinline__ void apply_strip(const Lds &L, const double *V, int64
     // --- Y += C1_s; W = T_s^T Y; C1_s -= W (first row wave of each group) ---
     if (c1w) {
       if (pf) {
+        // element e = 64u + lane is row 4u + lane/16: rows < ibw in all lanes
+        // for 4u + 4 <= ibw (uniform), per lane only in a ragged last group
 #pragma unroll
         for (int u = 0; u < CPF; ++u) {
           const int e = u * 64 + ln;
-          if (e < ibw * 16) yw[e] += pc[u];
+          if (4 * u + 4 <= ibw)
+            yw[e] += pc[u];
+          else if (4 * u < ibw && e < ibw * 16)
+            yw[e] += pc[u];
         }
       } else {
         c1_pass(yw, C1, ldc1, s, ibw, ncols, cg, true);
@@ -496,10 +563,17 @@ __device__ __forceinline__ void apply_strip(const Lds &L, const double *V, int64
     if (c1w) {
       if (pf) {
         gdbl *Cb = gp(C1) + (int64_t)col * ldc1 + s + (ln >> 4);
+        double w[CPF];
 #pragma unroll
-        for (int u = 0; u < CPF; ++u) {
-          const int a = 4 * u + (ln >> 4);
-          if (a < ibw && colok) Cb[4 * u] = pc[u] - yw[a * 16 + (ln & 15)];
+        for (int u = 0; u < CPF; ++u) w[u] = pc[u] - yw[u * 64 + ln];
+        if (colok) {
+#pragma unroll
+          for (int u = 0; u < CPF; ++u) {
+            if (4 * u + 4 <= ibw)
+              Cb[4 * u] = w[u];
+            else if (4 * u + (ln >> 4) < ibw)
+              Cb[4 * u] = w[u];
+          }
         }
         if (sn < kref) c1_load(pc, C1, ldc1, sn, min(ib, kref - sn), ncols, cg);
       } else {
@@ -525,6 +599,129 @@ __device__ __forceinline__ void apply_strip(const Lds &L, const double *V, int64
   store_c2(c2, C2, ldc2, vrows, col, colok && gact, rbase);
 }
 
+// Straight-line form of apply_strip for the common case: one row wave per
+// column group (tiles of at most 128 rows), a full 128-row V, a full 64-column
+// strip and whole IB blocks of 16 or 32 columns. No per-element predicates and
+// one block structure, so the compiler's wait counts stay exact across the
+// loop: the next block's V, T (issued when the current block is staged) and
+// C1 rows (issued after the current C1 write-back) are in flight while the
+// current block computes.
+template <int IB>
+__device__ __forceinline__ void apply_strip_fast(const Lds &L, const double *V, int64_t ldv,
+                                                 int kind, int kref, const double *T, int64_t ldt,
+                                                 double *C1, int64_t ldc1, double *C2,
+                                                 int64_t ldc2) {
+  constexpr int RW = 1, ROWS = Geo<RW>::ROWS, LDVC = Geo<RW>::LDVC;
+  constexpr int NQ = IB / 16;            // chunks per block
+  constexpr int VPL = NQ * 16 * ROWS / NTHR;  // V doubles per lane per block (8 or 16)
+  constexpr int LDTS = IB + 1;
+  static_assert(VPL <= PF, "V block exceeds the prefetch registers");
+  const int ln = lane_id(), wv = wave_id();
+  const int col = wv * 16 + (ln & 15);
+  ldbl *yw = L.y + wv * L.ibp * 16;
+  const bool c1 = C1 != nullptr;  // uniform
+  // per-lane staging positions: V element e = u*256 + tid -> column e / 128,
+  // row e % 128; T element e -> (e / IB, e % IB)
+  const int tid = tid_x();
+  const int vr = tid & (ROWS - 1), vc = tid >> 7;
+  d4 c2[RT];
+  {
+    const gdbl *Cc = gp(C2) + (int64_t)col * ldc2 + (ln >> 4);
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) c2[rt][r] = Cc[rt * 16 + 4 * r];
+  }
+  double pv[VPL], pt[IB * IB / NTHR > 0 ? IB * IB / NTHR : 1], pc[IB / 4];
+  constexpr int TPL = IB * IB / NTHR > 0 ? IB * IB / NTHR : 1;
+  auto load_v = [&](int s) {
+    const gdbl *Vb = gp(V) + (int64_t)(s + vc) * ldv + vr;
+#pragma unroll
+    for (int u = 0; u < VPL; ++u) {
+      const int gc = s + vc + 2 * u;
+      const double val = Vb[(int64_t)(2 * u) * ldv];
+      pv[u] = (kind == VK_UNIT) ? (vr < gc ? 0.0 : (vr == gc ? 1.0 : val)) : val;
+    }
+  };
+  auto load_t = [&](int s) {
+    const gdbl *Tb = gp(T) + (int64_t)s * ldt;
+#pragma unroll
+    for (int u = 0; u < TPL; ++u) {
+      const int e = u * NTHR + tid;
+      const int a = e / IB, c = e % IB;
+      const double val = Tb[min(a, IB - 1) + (int64_t)c * ldt];
+      pt[u] = (e < IB * IB && a <= c) ? val : 0.0;
+    }
+  };
+  auto load_c1 = [&](int s) {
+    const gdbl *Cb = gp(C1) + (int64_t)col * ldc1 + s + (ln >> 4);
+#pragma unroll
+    for (int u = 0; u < IB / 4; ++u) pc[u] = Cb[4 * u];
+  };
+  load_v(0);
+  load_t(0);
+  if (c1) load_c1(0);
+  for (int s = 0; s < kref; s += IB) {
+    __syncthreads();
+    {
+      ldbl *lb = L.vc + vc * LDVC + vr;
+#pragma unroll
+      for (int u = 0; u < VPL; ++u) lb[2 * u * LDVC] = pv[u];
+#pragma unroll
+      for (int u = 0; u < TPL; ++u) {
+        const int e = u * NTHR + tid;
+        if (e < IB * IB) L.ts[(e / IB) * LDTS + (e % IB)] = pt[u];
+      }
+    }
+    const int sn = s + IB;
+    if (sn < kref) {
+      load_v(sn);
+      load_t(sn);
+    }
+    __syncthreads();
+    y_group<RW>(L, kind, s, 0, NQ, ROWS, c2, yw, 0, false);
+    if (c1) {
+#pragma unroll
+      for (int u = 0; u < IB / 4; ++u) yw[u * 64 + ln] += pc[u];
+    }
+    wave_sync();
+    // W = T_s^T Y: every operand read before the block's result overwrites Y
+    d4 w[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) w[q] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int q2 = 0; q2 <= q; ++q2)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int arow = q2 * 16 + 4 * kk + (ln >> 4);
+          w[q] = mfma(L.ts[arow * LDTS + q * 16 + (ln & 15)], yw[arow * 16 + (ln & 15)], w[q]);
+        }
+    wave_sync();
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) yw[(q * 16 + 4 * r + (ln >> 4)) * 16 + (ln & 15)] = w[q][r];
+    wave_sync();
+    if (c1) {
+      gdbl *Cb = gp(C1) + (int64_t)col * ldc1 + s + (ln >> 4);
+#pragma unroll
+      for (int u = 0; u < IB / 4; ++u) Cb[4 * u] = pc[u] - yw[u * 64 + ln];
+      if (sn < kref) load_c1(sn);
+    }
+    update_group<RW>(L, kind, s, 0, NQ, ROWS, yw, c2, 0);
+  }
+  __syncthreads();
+  {
+    gdbl *Cc = gp(C2) + (int64_t)col * ldc2 + (ln >> 4);
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Cc[rt * 16 + 4 * r] = c2[rt][r];
+  }
+}
+
 // All columns of C2 (and C1), in strips of 16 * (4 / RW).
 template <int RW>
 __device__ __forceinline__ void apply_cols(const Lds &L, const double *V, int64_t ldv, int vrows,
@@ -533,9 +730,18 @@ __device__ __forceinline__ void apply_cols(const Lds &L, const double *V, int64_
                                            int64_t ldc2, int ncols) {
   constexpr int w = Geo<RW>::P;
   for (int c0 = 0; c0 < ncols; c0 += w) {
-    apply_strip<RW>(L, V, ldv, vrows, kind, kref, ib, T, ldt,
-                    C1 ? C1 + (int64_t)c0 * ldc1 : nullptr, ldc1, C2 + (int64_t)c0 * ldc2, ldc2,
-                    min(w, ncols - c0));
+    double *c1 = C1 ? C1 + (int64_t)c0 * ldc1 : nullptr;
+    double *c2 = C2 + (int64_t)c0 * ldc2;
+    const int nc = min(w, ncols - c0);
+    // uniform choice of the straight-line form
+    const bool fast = RW == 1 && vrows == TQ_ROWS_PER_WAVE && nc == w && kref % ib == 0 &&
+                      L.gmax * 16 >= ib;
+    if (fast && ib == 32)
+      apply_strip_fast<32>(L, V, ldv, kind, kref, T, ldt, c1, ldc1, c2, ldc2);
+    else if (fast && ib == 16)
+      apply_strip_fast<16>(L, V, ldv, kind, kref, T, ldt, c1, ldc1, c2, ldc2);
+    else
+      apply_strip<RW>(L, V, ldv, vrows, kind, kref, ib, T, ldt, c1, ldc1, c2, ldc2, nc);
   }
   __syncthreads();
 }
@@ -595,22 +801,17 @@ __device__ __forceinline__ void gram_cross(const Lds &L, const double *V, int64_
   const int cg = wv / RW, rb = wv % RW, rbase = rb * TQ_ROWS_PER_WAVE;
   const int col = cg * 16 + (ln & 15);
   const bool gact = cg * 16 < pw;
-  const gdbl *Vg = gp(V);
+  const gdbl *Vc = gp(V) + (int64_t)(a + min(col, pw - 1)) * ldv;
+  const int gc = a + col;
   d4 c2[RT];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = rbase + rt * 16 + 4 * r + (ln >> 4);
-      const int gc = a + col;
-      double v = 0.0;
-      if (col < pw && row < vrows) {
-        if (kind == VK_UNIT)
-          v = row < gc ? 0.0 : (row == gc ? 1.0 : Vg[row + (int64_t)gc * ldv]);
-        else
-          v = Vg[row + (int64_t)gc * ldv];
-      }
-      c2[rt][r] = v;
+      const double val = Vc[min(row, vrows - 1)];
+      const double y = kind == VK_UNIT ? (row < gc ? 0.0 : (row == gc ? 1.0 : val)) : val;
+      c2[rt][r] = (col < pw && row < vrows) ? y : 0.0;
     }
   ldbl *yw = L.y + cg * L.ibp * 16;
   const int nq = (a + 15) >> 4;
@@ -734,9 +935,10 @@ __device__ __forceinline__ void panel_task(const MatDesc &m, const Lds &L, bool 
   const int K = ts ? ncol : min(mrows, ncol);
   const int ln = lane_id(), wv = wave_id();
   const int cg = wv / RW, rb = wv % RW, rbase = rb * TQ_ROWS_PER_WAVE;
-  const int mc = cg * 16 + (ln & 15);  // my column within the register panel
-  const int g4 = ln >> 4;
-  gdbl *Xg = gp(X);
+  // panel layout: the four lanes of a column are adjacent (lane/4 = column
+  // within the wave's 16, lane%4 = row group), so column sums are DPP moves
+  const int mc = cg * 16 + (ln >> 2);  // my column within the register panel
+  const int g4 = ln & 3;
   gdbl *Rg = gp(R);
   gdbl *Tg = gp(Tp);
 
@@ -746,13 +948,7 @@ __device__ __forceinline__ void panel_task(const MatDesc &m, const Lds &L, bool 
     pw = ib <= P ? min(K - c0, (P / ib) * ib) : min(P, min(sg + ib, K) - c0);
     const bool colok = mc < pw;
     d4 x[RT];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = rbase + rt * 16 + 4 * r + g4;
-        x[rt][r] = (colok && row < mrows) ? Xg[row + (int64_t)(c0 + mc) * lda] : 0.0;
-      }
+    load_c2<true>(x, X + (int64_t)c0 * lda, lda, mrows, min(mc, pw - 1), colok, rbase);
     if (ts) {
       for (int e = tid_x(); e < P * P; e += NTHR) {
         const int a = e / P, c = e % P;
@@ -763,27 +959,36 @@ __device__ __forceinline__ void panel_task(const MatDesc &m, const Lds &L, bool 
     for (int c = 0; c < pw; ++c) {
       // lane-derived values recomputed per column (kept out of the loop's
       // live registers; see tid_x)
-      const int g4 = lane_id() >> 4;
-      const int mc = cg * 16 + (lane_id() & 15);
+      const int g4 = lane_id() & 3;
+      const int mc = cg * 16 + (lane_id() >> 2);
       const int j = c0 + c;
       const int h = ts ? -1 : j;  // rows > h form the reflector tail
       const int par = c & 1;
       const bool owner = cg == (c >> 4);
-      const bool mine = (lane_id() & 15) == (c & 15);
+      const bool mine = (lane_id() >> 2) == (c & 15);
       // --- norm of the tail and alpha (owner column group) ---
       double ss = 0.0, al = 0.0, alpha = 0.0;
       if (owner) {
+        // tiles wholly below the head row, wholly above it, or holding it
+        // (uniform tests; only the last needs per-row compares)
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
+        for (int rt = 0; rt < RT; ++rt) {
+          const int lo = rbase + rt * 16;
+          if (lo > h) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = rbase + rt * 16 + 4 * r + g4;
-            const double v = x[rt][r];
-            ss += row > h ? v * v : 0.0;
-            al += row == h ? v : 0.0;
+            for (int r = 0; r < 4; ++r) ss += x[rt][r] * x[rt][r];
+          } else if (lo + 15 >= h) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = lo + 4 * r + g4;
+              const double v = x[rt][r];
+              ss += row > h ? v * v : 0.0;
+              al += row == h ? v : 0.0;
+            }
           }
-        ss = col_sum(ss);
-        al = col_sum(al);
+        }
+        ss = quad_sum(ss);
+        al = quad_sum(al);
         if (ts) alpha = L.top[c * ld + c];
         if (RW > 1 && mine && g4 == 0) {
           L.red[2 * rb] = ss;
@@ -807,17 +1012,30 @@ __device__ __forceinline__ void panel_task(const MatDesc &m, const Lds &L, bool 
         householder(ts ? alpha : al, ss, beta, tau, scale);
         wave_sync();  // every lane has read alpha before R_jj is overwritten
         if (mine) {
-          ldbl *vb = L.vb + par * ROWS;
+          ldbl *vb = L.vb + par * ROWS + g4;
 #pragma unroll
-          for (int rt = 0; rt < RT; ++rt)
+          for (int rt = 0; rt < RT; ++rt) {
+            const int lo = rbase + rt * 16;
+            if (lo > h) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int row = rbase + rt * 16 + 4 * r + g4;
-              const double xv = x[rt][r];
-              const double v = row > h ? xv * scale : (row == h ? 1.0 : 0.0);
-              x[rt][r] = row > h ? v : (row == h ? beta : xv);
-              vb[row] = v;
+              for (int r = 0; r < 4; ++r) {
+                x[rt][r] *= scale;
+                vb[lo + 4 * r] = x[rt][r];
+              }
+            } else if (lo + 15 < h) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) vb[lo + 4 * r] = 0.0;
+            } else {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int row = lo + 4 * r + g4;
+                const double xv = x[rt][r];
+                const double v = row > h ? xv * scale : (row == h ? 1.0 : 0.0);
+                x[rt][r] = row > h ? v : (row == h ? beta : xv);
+                vb[lo + 4 * r] = v;
+              }
             }
+          }
           if (g4 == 0 && rb == 0) {
             L.taus[c] = tau;
             if (ts) L.top[c * ld + c] = beta;
@@ -834,7 +1052,7 @@ __device__ __forceinline__ void panel_task(const MatDesc &m, const Lds &L, bool 
         d0 += x[rt][0] * vb[rt * 16 + 0] + x[rt][2] * vb[rt * 16 + 8];
         d1 += x[rt][1] * vb[rt * 16 + 4] + x[rt][3] * vb[rt * 16 + 12];
       }
-      double d = col_sum(d0 + d1);
+      double d = quad_sum(d0 + d1);
       const bool active = mc > c && mc < pw;
       const double rtop = (ts && active) ? L.top[c * ld + mc] : 0.0;
       wave_sync();  // R_j row read by every lane of the column before it is written
@@ -860,13 +1078,7 @@ __device__ __forceinline__ void panel_task(const MatDesc &m, const Lds &L, bool 
     __syncthreads();
     panel_T<RW>(L, pw, ib);
     // --- write back the panel: R above, reflectors below ---
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = rbase + rt * 16 + 4 * r + g4;
-        if (colok && row < mrows) Xg[row + (int64_t)(c0 + mc) * lda] = x[rt][r];
-      }
+    store_c2<true>(x, X + (int64_t)c0 * lda, lda, mrows, mc, colok, rbase);
     __syncthreads();
     if (ts) {
       for (int e = tid_x(); e < pw * pw; e += NTHR) {
@@ -1009,12 +1221,21 @@ __device__ __forceinline__ MatDesc load_desc(const MatDesc *__restrict__ mats, i
   return m;
 }
 
-__device__ inline int ld_acquire(const int *p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// Counter poll: a relaxed agent-scope load reads the coherent value without
+// the cache invalidation an acquire load implies. On this multi-XCD chip an
+// agent-scope acquire invalidates the whole L2 of the XCD and a release
+// writes all of its dirty lines back, so the protocol does each once per
+// task (after the last wait, and after the task's stores), never per poll.
+__device__ inline int ld_relaxed(const int *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+
+// s_waitcnt vmcnt(0): this wave's global loads and stores have completed.
+__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // Thread 0 polls the task's counters; gives up (and flags `err`) after
 // `timeout` wall-clock ticks or when another workgroup flagged an error.
+// Returns after an agent-scope acquire (one L2 invalidation) and a barrier.
 __device__ __forceinline__ bool wait_deps(const Task &t, const MatDesc &m, const int *ctr, int *err,
                                           long long timeout) {
   __shared__ int s_ok;
@@ -1027,7 +1248,7 @@ __device__ __forceinline__ bool wait_deps(const Task &t, const MatDesc &m, const
       int target;
       task_wait(t, m, q, &idx, &target);
       unsigned spins = 0;
-      while (ld_acquire(ctr + idx) < target) {
+      while (ld_relaxed(ctr + idx) < target) {
         __builtin_amdgcn_s_sleep(2);
         if ((++spins & 63u) == 0) {
           if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
@@ -1042,6 +1263,7 @@ __device__ __forceinline__ bool wait_deps(const Task &t, const MatDesc &m, const
         }
       }
     }
+    if (ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     s_ok = ok;
   }
   __syncthreads();
@@ -1077,7 +1299,9 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
       case 32: run_task<2>(tk, m, make_lds<2>(lds_dyn, m)); break;
       default: run_task<4>(tk, m, make_lds<4>(lds_dyn, m)); break;
     }
-    __threadfence();
+    // Every wave's stores have reached the L2; then one agent-scope release
+    // (the L2 write-back) for the whole workgroup before the counters move.
+    wait_vm();
     __syncthreads();
     if (trace && threadIdx.x == 0) {
       trace[4 * t + 0] = t_take;
@@ -1086,9 +1310,10 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
       trace[4 * t + 3] = blockIdx.x;
     }
     if (threadIdx.x == 0 && use_waits) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       const int ns = task_nsignals(tk);
       for (int q = 0; q < ns; ++q)
-        __hip_atomic_fetch_add(ctr + task_signal(tk, m, q), 1, __ATOMIC_RELEASE,
+        __hip_atomic_fetch_add(ctr + task_signal(tk, m, q), 1, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
     }
   }

@@ -61,6 +61,7 @@ inline long long wall_clock64() { return 0; }
 inline void __builtin_amdgcn_s_sleep(int) { std::this_thread::yield(); }
 
 #define __builtin_amdgcn_fence(...) std::atomic_thread_fence(std::memory_order_seq_cst)
+#define __builtin_amdgcn_s_waitcnt(x) std::atomic_thread_fence(std::memory_order_seq_cst)
 #define __builtin_amdgcn_s_setprio(x) ((void)0)
 inline void __builtin_amdgcn_wave_barrier() { g_wave_bar[threadIdx.x >> 6]->arrive_and_wait(); }
 inline double __shfl(double v, int src, int width = 64) {
@@ -76,6 +77,23 @@ inline double __shfl_xor(double v, int mask, int width = 64) {
   g_wave_a[w][l] = v;
   g_wave_bar[w]->arrive_and_wait();
   double r = g_wave_a[w][l ^ mask];
+  g_wave_bar[w]->arrive_and_wait();
+  return r;
+}
+
+// DPP move within a row of 16 lanes, quad_perm patterns only (ctrl < 0x100):
+// lane l takes src from lane (l & ~3) | sel(l & 3).
+inline int __builtin_amdgcn_mov_dpp(int v, int ctrl, int, int, bool) {
+  int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  assert(ctrl < 0x100);
+  static thread_local int dummy;
+  (void)dummy;
+  double *slot = &g_wave_a[w][0];
+  int *islot = (int *)slot;  // reuse the exchange buffer as ints
+  islot[l] = v;
+  g_wave_bar[w]->arrive_and_wait();
+  int src = (l & ~3) | ((ctrl >> (2 * (l & 3))) & 3);
+  int r = islot[src];
   g_wave_bar[w]->arrive_and_wait();
   return r;
 }
