@@ -83,6 +83,24 @@ int64_t qr_T_size(int64_t M, int64_t N, int NB, int IB);
 int qr_factor(double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, double *T,
               void *stream);
 
+/* qr_factor for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, errors and results (A and T bit-identical to qr_factor's),
+ * but no hipMalloc, hipFree or other allocating call. Its dependency counters,
+ * ticket and error word live in a static device array of 16 MiB per device
+ * (4 Mi ints), looked up on the first call on a device; the DAG runs in the
+ * sequential program order of the tile algorithm, decoded on the device from
+ * each ticket, so no task list is stored (and no list schedule is used: it
+ * is slower than qr_factor). TILEQR_ERR_TOO_LARGE when the counters
+ * (min(MT,NT) + MT*NT*ceil(NB/strip) ints, strip = 64/32/16 columns for
+ * NB <= 128/256/512) exceed the array. Every call on a device shares that
+ * device's array, which keeps the last call's contents: calls that overlap
+ * on one device (on different streams) race. The array is cleared by a
+ * kernel at each call (no memset node). Watchdog errors are reported by
+ * qr_sync. */
+int qr_factor_noalloc(double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, double *T,
+                      void *stream);
+
 /* B <- Q^T B with Q from qr_factor(A, M, N, lda, NB, IB, T). NB and IB must
  * be the ones the factorization used (V and T depend on them); 0 resolves
  * through qr_tune(M, N, 1) as in qr_factor, which reproduces its choice as

@@ -112,6 +112,16 @@ def factor(A, nb=0, ib=0, T=None, stream=None):
     return A, T, nb, ib
 
 
+def factor_noalloc(A, nb, ib, T, stream=None):
+    """qr_factor_noalloc: the factorization without device allocations (T
+    supplied by the caller; the library's static scratch holds the rest)."""
+    M, N = A.shape
+    check(_lib.lib().qr_factor_noalloc(ctypes.c_void_p(A.data_ptr()), M, N, _ld(A), nb, ib,
+                                       ctypes.c_void_p(T.data_ptr()), _stream(stream)),
+          "qr_factor_noalloc")
+    return A, T
+
+
 def apply_Qt(A, T, nb, ib, B, stream=None):
     """B <- Q^T B in place (B column-major, M rows)."""
     M, N = A.shape

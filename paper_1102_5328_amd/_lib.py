@@ -29,6 +29,7 @@ SIGNATURES = {
     "qr_version": (ctypes.c_char_p, []),
     "qr_T_size": (c_i64, [c_i64, c_i64, c_int, c_int]),
     "qr_factor": (c_int, [c_vp, c_i64, c_i64, c_i64, c_int, c_int, c_vp, c_vp]),
+    "qr_factor_noalloc": (c_int, [c_vp, c_i64, c_i64, c_i64, c_int, c_int, c_vp, c_vp]),
     "qr_apply_Qt": (c_int, [c_vp, c_i64, c_i64, c_i64, c_int, c_int, c_vp, c_vp, c_i64, c_i64, c_vp]),
     "qr_factor_batched": (c_int, [c_vp, c_i64p, c_i64p, c_i64p, c_i64, c_intp, c_intp, c_vp, c_vp]),
     "qr_factor_loop": (c_int, [c_vp, c_i64p, c_i64p, c_i64p, c_i64, c_intp, c_intp, c_vp, c_vp]),

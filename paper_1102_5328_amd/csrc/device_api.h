@@ -30,3 +30,18 @@ hipError_t tq_launch_persistent(const TqLaunch &a, hipStream_t st);
 int tq_occupancy(size_t lds_bytes);
 hipError_t tq_launch_ssrfb_bench(double *buf, int nb, int ib, int calls, int grid, hipStream_t st);
 hipError_t tq_launch_fill(double *p, int64_t n, uint64_t seed, double scale, hipStream_t st);
+
+// Allocation-free factorization (qr_factor_noalloc): a static device array
+// of TQ_NOALLOC_SCRATCH_INTS ints per device; int 0 is the error word, int 1
+// the ticket, the dependency counters start at TQ_NOALLOC_CTR_OFFSET.
+#define TQ_NOALLOC_SCRATCH_INTS (4 << 20)
+#define TQ_NOALLOC_CTR_OFFSET 64
+// Device address of the array on device `dev` (looked up once with
+// hipGetSymbolAddress while `dev` is current); 0 or a negative code.
+int tq_noalloc_scratch(int dev, int **ptr);
+// The address if it was looked up on `dev` already, else nullptr.
+int *tq_noalloc_scratch_if_set(int dev);
+// Zeroes the ticket and counters, then runs the persistent kernel over the
+// program-order DAG of one matrix (tasks decoded from the ticket).
+hipError_t tq_launch_noalloc(int *scratch_ptr, const MatDesc &md, int64_t ntasks, int64_t nctr,
+                             int grid, size_t lds, long long timeout, hipStream_t st);

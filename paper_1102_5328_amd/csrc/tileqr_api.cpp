@@ -86,6 +86,15 @@ struct Plan {
   }
 };
 
+// Device facts of the allocation-free entry point (no error word of its own:
+// it lives in the static scratch).
+struct NoallocDev {
+  bool init = false;
+  int ncu = 0;
+  long long wall_khz = 100000;
+};
+NoallocDev g_noalloc[64];
+
 // Compute units the persistent grid and its schedule are sized for (0: all
 // of the device); see qr_set_compute_units.
 int g_cu_limit = 0;
@@ -395,6 +404,68 @@ int qr_factor(double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, doub
   return factor_one(A, M, N, lda, NB, IB, T, (hipStream_t)stream, *ds);
 }
 
+int qr_factor_noalloc(double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, double *T,
+                      void *stream) {
+  if (M < 0) return -2;
+  if (N < 0) return -3;
+  if (!A && M * N > 0) return -1;
+  if (lda < std::max<int64_t>(1, M)) return -4;
+  if (NB != 0 && !nb_ok(NB)) return -5;
+  if (IB < 0 || (NB != 0 && IB > NB)) return -6;
+  if (M > INT32_MAX || N > INT32_MAX) return TILEQR_ERR_TOO_LARGE;
+  int rc = resolve_tiling(M, N, 1, &NB, &IB);
+  if (rc) return rc;
+  if (!nb_ok(NB)) return -5;
+  if (IB < 1 || IB > NB) return -6;
+  if (!T && M * N > 0) return -7;
+  if (!nb_enabled(NB)) return TILEQR_ERR_DISABLED;
+  if (M == 0 || N == 0) return 0;
+  MatDesc md;
+  std::memset(&md, 0, sizeof(md));
+  md_setup(md, M, N, NB, IB, 0);
+  md.lda = lda;
+  md.A = A;
+  md.T = T;
+  const int64_t nctr = ctr_count_factor(md);
+  if (TQ_NOALLOC_CTR_OFFSET + nctr > TQ_NOALLOC_SCRATCH_INTS) return TILEQR_ERR_TOO_LARGE;
+  // tasks of the program order (as the device decodes them)
+  int64_t ntasks = 0;
+  const int64_t slast = strips_of(md, md.NT - 1);
+  for (int64_t k = 0; k < md.KT; ++k) {
+    const int64_t r = md.MT - 1 - k, c = md.NT - 1 - k;
+    const int64_t cs = c >= 1 ? (c - 1) * md.S + slast : 0;
+    ntasks += 1 + r + cs + r * cs;
+  }
+  if (ntasks >= INT32_MAX) return TILEQR_ERR_TOO_LARGE;
+  std::lock_guard<std::mutex> lk(g_mu);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return TILEQR_ERR_NODEVICE;
+  NoallocDev &nd = g_noalloc[dev];
+  if (!nd.init) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return TILEQR_ERR_NODEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return TILEQR_ERR_NODEVICE;
+    nd.ncu = prop.multiProcessorCount;
+    int khz = 0;
+    nd.wall_khz = (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess &&
+                   khz > 0) ? khz : 100000;
+    nd.init = true;
+  }
+  int *sp = nullptr;
+  if (tq_noalloc_scratch(dev, &sp) != 0) return TILEQR_ERR_HIP;
+  const size_t lds = (size_t)lds_plan(NB, IB).doubles * 8;
+  const int occ = tq_occupancy(lds);
+  const int units = units_for(M, N, 1);
+  const int cus = (units > 0 && units < nd.ncu) ? units : nd.ncu;
+  const int grid = (int)std::min<int64_t>((int64_t)cus * occ, ntasks);
+  DevState tmp;
+  tmp.wall_khz = nd.wall_khz;
+  if (tq_launch_noalloc(sp, md, ntasks, nctr, std::max(1, grid), lds, watchdog_ticks(tmp),
+                        (hipStream_t)stream) != hipSuccess)
+    return TILEQR_ERR_HIP;
+  return 0;
+}
+
 int qr_apply_Qt(const double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB,
                 const double *T, double *B, int64_t nrhs, int64_t ldb, void *stream) {
   if (M < 0) return -2;
@@ -564,6 +635,17 @@ int qr_sync(void *stream) {
   int e = 0;
   if (hipMemcpy(&e, ds->err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
     return TILEQR_ERR_HIP;
+  int dev = 0;
+  hipGetDevice(&dev);
+  if (int *sp = tq_noalloc_scratch_if_set(dev)) {
+    int e2 = 0;
+    if (hipMemcpy(&e2, sp, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+      return TILEQR_ERR_HIP;
+    if (e2 != 0) {
+      hipMemset(sp, 0, sizeof(int));
+      if (e == 0) e = e2;
+    }
+  }
   if (e != 0) {
     hipMemset(ds->err, 0, sizeof(int));
     hipDeviceSynchronize();

@@ -1272,24 +1272,65 @@ __device__ __forceinline__ bool wait_deps(const Task &t, const MatDesc &m, const
   return ok != 0;
 }
 
+// Task t of the factorization DAG of one matrix in the sequential program
+// order of the tile algorithm (step k: GEQRT, the TSQRT chain, the LARFBs,
+// then the SSRFBs with i ascending), which is a topological order. (k, pk)
+// carry the step of the previous decode and the number of tasks before it;
+// tickets of one workgroup only grow, so the scan over k is amortized O(1).
+__device__ inline Task decode_program_order(const MatDesc &m, int64_t t, int &k, int64_t &pk) {
+  const int S = m.S, slast = strips_of(m, m.NT - 1);
+  for (;;) {
+    const int64_t r = m.MT - 1 - k, c = m.NT - 1 - k;
+    const int64_t cs = c >= 1 ? (c - 1) * S + slast : 0;
+    const int64_t cnt = 1 + r + cs + r * cs;
+    if (t < pk + cnt) {
+      const int64_t o = t - pk;
+      if (o == 0) return make_task(TK_GEQRT, 0, k, k, k, 0);
+      if (o <= r) return make_task(TK_TSQRT, 0, (int)(k + o), k, k, 0);
+      if (o <= r + cs) {
+        const int64_t idx = o - 1 - r;
+        return make_task(TK_LARFB, 0, k, (int)(k + 1 + idx / S), k, (int)(idx % S));
+      }
+      const int64_t idx = o - 1 - r - cs, rem = idx % cs;
+      return make_task(TK_SSRFB, 0, (int)(k + 1 + idx / cs), (int)(k + 1 + rem / S), k,
+                       (int)(rem % S));
+    }
+    pk += cnt;
+    ++k;
+  }
+}
+
 __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(2, 2))) void tq_persistent(
     const Task *__restrict__ tasks, int64_t ntasks, MatDesc single,
     const MatDesc *__restrict__ mats, int *ctr, unsigned int *ticket, int *err, int use_waits,
     long long timeout, long long *trace) {
   extern __shared__ double lds_dyn[];
   __shared__ int s_t;
+  __shared__ Task s_task;
+  int dk = 0;       // program-order decode state (thread 0, tasks == nullptr)
+  int64_t dpk = 0;
   for (;;) {
     if (threadIdx.x == 0) {
       const int e = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      s_t = e ? -1 : (int)atomicAdd(ticket, 1u);
+      const int tt = e ? -1 : (int)atomicAdd(ticket, 1u);
+      s_t = tt;
+      if (!tasks && tt >= 0 && tt < ntasks) s_task = decode_program_order(single, tt, dk, dpk);
     }
     __syncthreads();
     // Uniform across the workgroup: read into a scalar register so that the
     // task's parameters (and every loop bound derived from them) are scalar.
     const int64_t t = __builtin_amdgcn_readfirstlane(s_t);
+    Task tk;
+    if (tasks && t >= 0 && t < ntasks) {
+      tk = tasks[t];
+    } else {
+      tk.w0 = __builtin_amdgcn_readfirstlane(s_task.w0);
+      tk.i = __builtin_amdgcn_readfirstlane(s_task.i);
+      tk.j = __builtin_amdgcn_readfirstlane(s_task.j);
+      tk.k = __builtin_amdgcn_readfirstlane(s_task.k);
+    }
     __syncthreads();
     if (t < 0 || t >= ntasks) break;
-    const Task tk = tasks[t];
     const MatDesc m = load_desc(mats, task_mat(tk), single);
     const long long t_take = trace ? wall_clock64() : 0;
     if (use_waits && !wait_deps(tk, m, ctr, err, timeout)) break;
@@ -1411,5 +1452,48 @@ hipError_t tq_launch_fill(double *p, int64_t n, uint64_t seed, double scale, hip
   int g = (int)((n + 255) / 256);
   g = g > 4096 ? 4096 : (g < 1 ? 1 : g);
   hipLaunchKernelGGL(tq_fill_hash, dim3(g), dim3(256), 0, st, p, n, seed, scale);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free factorization: a static device array holds everything the
+// persistent launch needs besides A and T (error word, ticket, dependency
+// counters); the tasks are decoded from the ticket in program order, so no
+// task list is stored either.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) int scratch[TQ_NOALLOC_SCRATCH_INTS];
+
+namespace {
+int *g_scratch_ptr[64];  // device address of `scratch`, per device (null: not looked up)
+}
+
+int tq_noalloc_scratch(int dev, int **ptr) {
+  if (dev < 0 || dev >= 64) return -1;
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return -2;
+    g_scratch_ptr[dev] = (int *)p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return 0;
+}
+
+int *tq_noalloc_scratch_if_set(int dev) {
+  return (dev >= 0 && dev < 64) ? g_scratch_ptr[dev] : nullptr;
+}
+
+hipError_t tq_launch_noalloc(int *sp, const MatDesc &md, int64_t ntasks, int64_t nctr, int grid,
+                             size_t lds, long long timeout, hipStream_t st) {
+  // ticket and counters start at zero; the error word is left to qr_sync
+  const int64_t nz = TQ_NOALLOC_CTR_OFFSET - 1 + nctr;
+  int g = (int)((nz + 255) / 256);
+  g = g > 1024 ? 1024 : (g < 1 ? 1 : g);
+  hipLaunchKernelGGL(tq_zero_ints, dim3(g), dim3(256), 0, st, sp + 1, nz);
+  hipError_t e = set_lds((const void *)tq_persistent, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(tq_persistent, dim3(grid), dim3(NTHR), lds, st, (const Task *)nullptr, ntasks,
+                     md, (const MatDesc *)nullptr, sp + TQ_NOALLOC_CTR_OFFSET,
+                     (unsigned int *)(sp + 1), sp, 1, timeout, (long long *)nullptr);
   return hipGetLastError();
 }

@@ -15,6 +15,10 @@ void oracle_geqr2(int64_t m, int64_t n, double *a, int64_t lda, double *tau);
 void oracle_apply_qt(int64_t m, int64_t k, const double *v, int64_t ldv, const double *tau, int64_t nrhs, double *b, int64_t ldb);
 }
 
+// Tasks decoded on the device from the ticket in program order (the
+// allocation-free entry point's launch): no task list.
+static bool g_decode = false;
+
 static int run(std::vector<MatDesc> mats, bool apply, int grid) {
   size_t lds = 0; int64_t c = 0;
   for (auto &m : mats) { m.ctr = c; c += apply ? ctr_count_apply(m) : ctr_count_factor(m); lds = std::max(lds, (size_t)lds_plan(m.nb, m.ib).doubles * 8); }
@@ -25,6 +29,7 @@ static int run(std::vector<MatDesc> mats, bool apply, int grid) {
   std::vector<MatDesc> dm = mats;
   TqLaunch a;
   a.tasks = order.data(); a.ntasks = order.size(); a.single = mats[0]; a.mats = mats.size() > 1 ? dm.data() : nullptr;
+  if (g_decode && !apply && mats.size() == 1) a.tasks = nullptr;  // same count: every task once
   a.ctr = ctr.data(); a.ctr_base = ctr.data(); a.nctr_zero = nctr + 1; a.ticket = (unsigned *)(ctr.data() + nctr);
   a.trace = nullptr; a.err = &err; a.use_waits = 1; a.timeout = 1LL << 60; a.lds_bytes = lds; a.grid = grid;
   tq_launch_persistent(a, nullptr);
@@ -81,6 +86,7 @@ static int batch_main(int count, int seed) {
 
 int main(int argc, char **argv) {
   if (std::string(argv[1]) == "batch") return batch_main(atoi(argv[2]), atoi(argv[3]));
+  if (std::string(argv[1]) == "decode") { g_decode = true; ++argv; }
   int M = atoi(argv[1]), N = atoi(argv[2]), nb = atoi(argv[3]), ib = atoi(argv[4]);
   int64_t lda = M;
   std::mt19937_64 g(M * 7 + N);

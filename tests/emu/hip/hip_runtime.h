@@ -31,6 +31,8 @@ extern dim3 blockDim, gridDim;
 #define __launch_bounds__(...)
 #define __restrict__
 #define __shared__ static
+#define __align__(x) __attribute__((aligned(x)))
+#define HIP_SYMBOL(x) ((const void *)&(x))
 
 typedef int hipError_t;
 #define hipSuccess 0
@@ -45,6 +47,7 @@ inline hipError_t hipGetDevice(int *d) { *d = 0; return 0; }
 template <class T> inline hipError_t hipMalloc(T **p, size_t n) { *p = (T *)malloc(n); return *p ? 0 : 1; }
 inline hipError_t hipFree(void *p) { free(p); return 0; }
 inline hipError_t hipMemcpy(void *d, const void *s, size_t n, int) { memcpy(d, s, n); return 0; }
+inline hipError_t hipGetSymbolAddress(void **p, const void *sym) { *p = (void *)sym; return 0; }
 
 extern std::barrier<> *g_block_bar;
 extern std::barrier<> *g_wave_bar[4];

@@ -48,6 +48,17 @@ def test_tile_qr_emulated(emu, M, N, nb, ib):
     assert "R_rel" in out
 
 
+@pytest.mark.parametrize("M,N,nb,ib", [
+    (200, 150, 64, 16),    # tall: the last steps have no LARFB (r > 0, c = 0)
+    (150, 230, 64, 32),    # wide: the last step has no TSQRT (r = 0), ragged last strip
+])
+def test_program_order_decode_emulated(emu, M, N, nb, ib):
+    # tasks decoded from the ticket in program order (no task list), as the
+    # allocation-free entry point launches them
+    out = _run([emu[0], "decode", str(M), str(N), str(nb), str(ib)])
+    assert "R_rel" in out
+
+
 def test_batched_emulated(emu):
     out = _run([emu[0], "batch", "3", "2"])
     assert "worst R_rel" in out

@@ -64,6 +64,24 @@ def test_factor_argument_errors(lib):
     assert f(p, 8, 4, 8, 256, 32, p, None) == 8  # TILEQR_ERR_DISABLED
 
 
+def test_factor_noalloc_argument_errors(lib):
+    # the same checks as qr_factor, then the static scratch's size limit; all
+    # of them return before any device call
+    f = lib.qr_factor_noalloc
+    p = ctypes.c_void_p(16)  # never dereferenced
+    assert f(p, -1, 4, 4, 64, 16, p, None) == -2
+    assert f(p, 4, -1, 4, 64, 16, p, None) == -3
+    assert f(None, 4, 4, 4, 64, 16, p, None) == -1
+    assert f(p, 8, 4, 7, 64, 16, p, None) == -4
+    assert f(p, 8, 4, 8, 8, 4, p, None) == -5
+    assert f(p, 8, 4, 8, 64, 65, p, None) == -6
+    assert f(p, 8, 4, 8, 64, 16, None, None) == -7
+    # 65536 x 16384 with NB = 16: 4096 x 1024 tiles, one strip each, plus
+    # 1024 panel counters: more than the 4 Mi ints of the scratch
+    assert f(p, 65536, 16384, 65536, 16, 16, p, None) == 5  # TILEQR_ERR_TOO_LARGE
+    assert f(p, 0, 16, 1, 64, 16, p, None) == 0  # empty: nothing to do
+
+
 def test_apply_argument_errors(lib):
     f = lib.qr_apply_Qt
     p = ctypes.c_void_p(16)
