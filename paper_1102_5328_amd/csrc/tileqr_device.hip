@@ -903,17 +903,79 @@ __device__ inline void t_column(const Lds &L, int cc, int tb) {
 }
 
 // The T blocks of a register panel of pw columns, from the Gram entries and
-// tau in LDS: blocks of ib columns (one per wave, round robin) when IB <= P,
-// else the panel's own diagonal block.
+// tau in LDS (T blocks of ib columns when IB <= P, else the panel's own
+// diagonal block). First the recurrence runs on sub-blocks of at most 16
+// columns, one wave per sub-block; then each T block is assembled from its
+// sub-blocks by one wave, 16 columns at a time, on the MFMA:
+//   T[0:a, a:a+w] = -T[0:a, 0:a] (G[0:a, a:a+w] T[a:a+w, a:a+w]),
+// with the product in the lower bracket kept in registers in the
+// accumulator layout, which is the B-operand layout of the next product.
 template <int RW>
 __device__ inline void panel_T(const Lds &L, int pw, int ib) {
-  constexpr int P = Geo<RW>::P;
-  const int wv = wave_id();
-  const int bw = ib <= P ? ib : pw;
+  constexpr int P = Geo<RW>::P, ld = P + 1;
+  constexpr int NZ = P / 16;  // row tiles of a T block (at most)
+  const int wv = wave_id(), ln = lane_id();
+  const int bw = ib <= P ? ib : pw;  // T block width
   const int nblk = (pw + bw - 1) / bw;
-  for (int b = wv; b < nblk; b += 4) {
-    const int tb = b * bw, te = min(tb + bw, pw);
+  // sub-block recurrences
+  const int nsub_b = (bw + 15) / 16;  // sub-blocks per T block
+  for (int sb = wv; sb < nblk * nsub_b; sb += 4) {
+    const int b = sb / nsub_b, q = sb % nsub_b;
+    const int tb = b * bw + q * 16;
+    const int te = min(min(tb + 16, b * bw + bw), pw);
     for (int cc = tb; cc < te; ++cc) t_column<RW>(L, cc, tb);
+  }
+  if (nsub_b == 1) return;
+  __syncthreads();
+  // assembly of each T block from its sub-blocks (one wave per block)
+  for (int b = wv; b < nblk; b += 4) {
+    const int t0 = b * bw, tw = min(bw, pw - t0);
+    for (int a = 16; a < tw; a += 16) {
+      const int w = min(16, tw - a);
+      const int na = a / 16;  // row tiles above
+      d4 z[NZ];
+      // Z = G[0:a, a:a+w] T[a:a+w, a:a+w]: A = G[i][a+k] = tg[(t0+a+k)][t0+i],
+      // B = T[a+k][a+j] (upper, k <= j, j < w)
+#pragma unroll
+      for (int it = 0; it < NZ; ++it) {
+        z[it] = d4{0.0, 0.0, 0.0, 0.0};
+        if (it < na) {
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const int k = 4 * kk + (ln >> 4), i = it * 16 + (ln & 15), j = ln & 15;
+            const int kc = min(k, w - 1), jc = min(j, w - 1);  // in-range addresses
+            const double ga = k < w ? (double)L.tg[(t0 + a + kc) * ld + t0 + i] : 0.0;
+            const double tb_ = (k <= j && j < w) ? (double)L.tg[(t0 + a + kc) * ld + t0 + a + jc] : 0.0;
+            z[it] = mfma(ga, tb_, z[it]);
+          }
+        }
+      }
+      // X = T[0:a, 0:a] Z: output row tile it, k over row tiles it2 >= it of Z
+#pragma unroll
+      for (int it = 0; it < NZ; ++it) {
+        if (it < na) {
+          d4 xacc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int it2 = 0; it2 < NZ; ++it2) {
+            if (it2 >= it && it2 < na) {
+#pragma unroll
+              for (int kk = 0; kk < 4; ++kk) {
+                const int i = it * 16 + (ln & 15), k = it2 * 16 + 4 * kk + (ln >> 4);
+                const double ta = i <= k ? (double)L.tg[(t0 + i) * ld + t0 + k] : 0.0;
+                xacc = mfma(ta, z[it2][kk], xacc);
+              }
+            }
+          }
+          // T[it*16 + row][a + j] = -X (rows < a, columns a.. a+w: not read above)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = it * 16 + 4 * r + (ln >> 4), j = ln & 15;
+            if (j < w) L.tg[(t0 + i) * ld + t0 + a + j] = -xacc[r];
+          }
+        }
+      }
+      wave_sync();
+    }
   }
 }
 
@@ -971,23 +1033,24 @@ __device__ __forceinline__ void panel_task(const MatDesc &m, const Lds &L, bool 
       if (owner) {
         // tiles wholly below the head row, wholly above it, or holding it
         // (uniform tests; only the last needs per-row compares)
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};  // independent chains
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
           const int lo = rbase + rt * 16;
           if (lo > h) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) ss += x[rt][r] * x[rt][r];
+            for (int r = 0; r < 4; ++r) s4[r] += x[rt][r] * x[rt][r];
           } else if (lo + 15 >= h) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int row = lo + 4 * r + g4;
               const double v = x[rt][r];
-              ss += row > h ? v * v : 0.0;
+              s4[r] += row > h ? v * v : 0.0;
               al += row == h ? v : 0.0;
             }
           }
         }
-        ss = quad_sum(ss);
+        ss = quad_sum((s4[0] + s4[1]) + (s4[2] + s4[3]));
         al = quad_sum(al);
         if (ts) alpha = L.top[c * ld + c];
         if (RW > 1 && mine && g4 == 0) {
@@ -1012,7 +1075,7 @@ __device__ __forceinline__ void panel_task(const MatDesc &m, const Lds &L, bool 
         householder(ts ? alpha : al, ss, beta, tau, scale);
         wave_sync();  // every lane has read alpha before R_jj is overwritten
         if (mine) {
-          ldbl *vb = L.vb + par * ROWS + g4;
+          ldbl *vb = L.vb + par * ROWS + 4 * g4;  // [tile][g4][r]
 #pragma unroll
           for (int rt = 0; rt < RT; ++rt) {
             const int lo = rbase + rt * 16;
@@ -1020,11 +1083,11 @@ __device__ __forceinline__ void panel_task(const MatDesc &m, const Lds &L, bool 
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
                 x[rt][r] *= scale;
-                vb[lo + 4 * r] = x[rt][r];
+                vb[lo + r] = x[rt][r];
               }
             } else if (lo + 15 < h) {
 #pragma unroll
-              for (int r = 0; r < 4; ++r) vb[lo + 4 * r] = 0.0;
+              for (int r = 0; r < 4; ++r) vb[lo + r] = 0.0;
             } else {
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
@@ -1032,7 +1095,7 @@ __device__ __forceinline__ void panel_task(const MatDesc &m, const Lds &L, bool 
                 const double xv = x[rt][r];
                 const double v = row > h ? xv * scale : (row == h ? 1.0 : 0.0);
                 x[rt][r] = row > h ? v : (row == h ? beta : xv);
-                vb[lo + 4 * r] = v;
+                vb[lo + r] = v;
               }
             }
           }
@@ -1045,14 +1108,13 @@ __device__ __forceinline__ void panel_task(const MatDesc &m, const Lds &L, bool 
       __syncthreads();
       // --- dot products of every column with v ---
       const double tau = L.taus[c];
-      const ldbl *vb = L.vb + par * ROWS + rbase + g4;
-      double d0 = 0.0, d1 = 0.0;
+      const ldbl *vb = L.vb + par * ROWS + rbase + 4 * g4;  // [tile][g4][r]
+      double dd[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt) {
-        d0 += x[rt][0] * vb[rt * 16 + 0] + x[rt][2] * vb[rt * 16 + 8];
-        d1 += x[rt][1] * vb[rt * 16 + 4] + x[rt][3] * vb[rt * 16 + 12];
-      }
-      double d = quad_sum(d0 + d1);
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dd[r] += x[rt][r] * vb[rt * 16 + r];
+      double d = quad_sum((dd[0] + dd[1]) + (dd[2] + dd[3]));
       const bool active = mc > c && mc < pw;
       const double rtop = (ts && active) ? L.top[c * ld + mc] : 0.0;
       wave_sync();  // R_j row read by every lane of the column before it is written
@@ -1068,7 +1130,7 @@ __device__ __forceinline__ void panel_task(const MatDesc &m, const Lds &L, bool 
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) x[rt][r] -= f * vb[rt * 16 + 4 * r];
+          for (int r = 0; r < 4; ++r) x[rt][r] -= f * vb[rt * 16 + r];
         if (ts && g4 == 0 && rb == 0) L.top[c * ld + mc] = rtop - f;
       }
       // Gram entry G[mc][c] of two reflectors of the same T block
