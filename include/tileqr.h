@@ -72,8 +72,7 @@ int64_t qr_T_size(int64_t M, int64_t N, int NB, int IB);
  *      (i, k), i > k, the full vectors of DTSQRT.
  *  NB  tile order, 16 <= NB <= 512; IB inner block, 1 <= IB <= NB (IB need
  *      not divide NB: the last block of a tile is narrower). NB = 0 or IB = 0:
- *      taken from qr_tune(M, N, 1). The tile classes above
- *      NB = 128 are currently switched off (TILEQR_ERR_DISABLED). The
+ *      taken from qr_tune(M, N, 1). The
  *      persistent grid is sized for qr_tune_units(M, N, 1) compute units.
  *  T   (out, device, qr_T_size(M, N, NB, IB) doubles): the T factors.
  * One persistent kernel runs the whole DAG; the dependency counters and the

@@ -23,7 +23,7 @@
 
 // Largest tile order the library accepts (TILEQR_ERR_DISABLED above it).
 #ifndef TQ_MAX_ENABLED_NB
-#define TQ_MAX_ENABLED_NB 128
+#define TQ_MAX_ENABLED_NB 512
 #endif
 
 TQ_HD inline int rw_for_nb(int nb) { return nb <= 128 ? 1 : nb <= 256 ? 2 : 4; }

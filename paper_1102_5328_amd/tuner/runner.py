@@ -15,7 +15,7 @@ from .. import inputs
 from . import heuristics as H
 from . import step2 as S2
 
-ENABLED_MAX_NB = 128  # tile classes above are switched off in the library
+ENABLED_MAX_NB = 512  # largest tile order the library accepts
 
 
 def config2_pairs(nbs=(64, 96, 128, 192, 256, 384, 512), ib_min=16, max_nb=ENABLED_MAX_NB):

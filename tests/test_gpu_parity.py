@@ -11,11 +11,8 @@ from helpers import check_factorization, factor_gpu, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
-# Tile classes above NB = 128 are switched off in the library: an earlier
-# build of the NB <= 256 class made a device memory fault whose cause is not
-# established (the CPU emulation of the same source shows no out-of-bounds
-# access), so they are not run on the GPU.
-NB_OFF = "NB > 128 switched off pending the cause of a device fault"
+# Tile orders above 128 run the same kernels with two or four row waves per
+# column group (128-row slabs per wave).
 
 
 def _assert_ok(r):
@@ -47,8 +44,10 @@ def test_config1_512_nb128_ib32(units):
     (64, 512, 64, 16),      # one tile row
     (700, 64, 64, 64),      # one tile column (the TSQRT chain only)
     (33, 33, 16, 1),        # IB = 1
-    pytest.param(520, 520, 256, 32, marks=pytest.mark.skip(reason=NB_OFF)),
-    pytest.param(600, 600, 512, 64, marks=pytest.mark.skip(reason=NB_OFF)),
+    (520, 520, 256, 32),    # two row waves per column group
+    (600, 600, 512, 64),    # four row waves
+    (450, 430, 192, 96),    # IB wider than the 32-column register panel
+    (530, 300, 384, 384),   # IB = NB = 384, T assembled over 16-column panels
 ])
 def test_factor_shapes(M, N, nb, ib):
     A = inputs.uniform(M, N, seed=M * 7 + N)
@@ -67,8 +66,7 @@ def test_leading_dimension_padding():
                                        (64, 16, 64, 16), (70, 12, 128, 12),
                                        (64, 64, 64, 16), (100, 60, 128, 32), (50, 90, 64, 24),
                                        (128, 128, 128, 128),
-                                       pytest.param(256, 200, 256, 48,
-                                                    marks=pytest.mark.skip(reason=NB_OFF))])
+                                       (256, 200, 256, 48), (512, 100, 512, 128)])
 def test_single_tile_reflectors_match_oracle(M, N, nb, ib):
     """M, N <= NB: qr_factor is one DGEQRT, so V and tau = diag(T_s) equal the
     unblocked oracle's reflectors up to rounding, for any IB."""

@@ -61,7 +61,6 @@ def test_factor_argument_errors(lib):
     assert f(p, 8, 4, 8, 64, 65, p, None) == -6
     assert f(p, 8, 4, 8, 64, -1, p, None) == -6
     assert f(p, 8, 4, 8, 64, 16, None, None) == -7
-    assert f(p, 8, 4, 8, 256, 32, p, None) == 8  # TILEQR_ERR_DISABLED
 
 
 def test_factor_noalloc_argument_errors(lib):
