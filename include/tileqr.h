@@ -91,7 +91,7 @@ int qr_factor(double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, doub
  * sequential program order of the tile algorithm, decoded on the device from
  * each ticket, so no task list is stored (and no list schedule is used: it
  * is slower than qr_factor). TILEQR_ERR_TOO_LARGE when the counters
- * (min(MT,NT) + MT*NT*ceil(NB/strip) ints, strip = 64/32/16 columns for
+ * (min(MT,NT)*MT + MT*NT*ceil(NB/strip) ints, strip = 64/32/16 columns for
  * NB <= 128/256/512) exceed the array. Every call on a device shares that
  * device's array, which keeps the last call's contents: calls that overlap
  * on one device (on different streams) race. The array is cleared by a
@@ -109,6 +109,31 @@ int qr_factor_noalloc(double *A, int64_t M, int64_t N, int64_t lda, int NB, int 
  * -9 nrhs < 0, -10 ldb. */
 int qr_apply_Qt(const double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB,
                 const double *T, double *B, int64_t nrhs, int64_t ldb, void *stream);
+
+/* Communication-avoiding variant (Section 7: the tile rows split into p
+ * domains, each reduced by its own GEQRT + TSQRT chain, the domains' R
+ * factors merged pairwise over a binary tree), so the panel of a tall matrix
+ * is reduced in parallel instead of by one chain of MT tasks. p = 1 is the
+ * flat tree of qr_factor (same results bit for bit); p = 0 takes the decision
+ * table's domain count; p > MT is taken as MT (one tile row per domain). The
+ * domains hold h = ceil(MT / p) consecutive tile rows.
+ *  A   (in/out): R in the upper triangle/trapezoid as in qr_factor; below
+ *      it the reflectors of the domains' GEQRT (unit-lower part of each
+ *      domain's first tile) and TSQRT (full tiles); the upper parts of the
+ *      domains' first tiles below the diagonal hold their R before merging.
+ *  T   (out, device, qr_T_size_ca(M, N, NB, IB, p) doubles): the per-tile T
+ *      factors as in qr_factor, then the merges' reflector blocks
+ *      (min(MT,NT) x domains blocks of NB x NB) and their T factors.
+ * Errors as qr_factor with p in position 7: -7 p < 0, -8 T null. */
+int64_t qr_T_size_ca(int64_t M, int64_t N, int NB, int IB, int p);
+int qr_factor_ca(double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, int p, double *T,
+                 void *stream);
+
+/* B <- Q^T B with Q from qr_factor_ca(A, M, N, lda, NB, IB, p, T) (the same
+ * NB, IB and p). Errors as qr_apply_Qt with p in position 7: -7 p < 0,
+ * -8 T, -9 B, -10 nrhs, -11 ldb. */
+int qr_apply_Qt_ca(const double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, int p,
+                   const double *T, double *B, int64_t nrhs, int64_t ldb, void *stream);
 
 /* Many independent factorizations of uneven sizes in ONE persistent launch
  * over the union of their DAGs, each matrix with its own (NB, IB); the
@@ -192,7 +217,10 @@ int qr_ssrfb_bench_flush(int NB, int IB, int calls, int workers, int64_t flush_b
  * `batch` matrices: TILEQR_NB / TILEQR_IB environment overrides first, then
  * the learned cost model if one is loaded and confident, then the decision
  * table's nearest benchmarked configuration (Section 6.1: nearest in
- * log M, log N, log batch; ties to the larger size), else the install
+ * log M, log N, log batch; ties to the larger size) within the table section
+ * tuned for the caller's compute units (the qr_set_compute_units setting,
+ * else the whole device; the section whose budget is nearest in log scale,
+ * as the paper interpolates over the core count), else the install
  * default (NB=128, IB=32, or the table's "default" line). *source: 0
  * default, 1 table, 2 model, 3 env;
  * +8 when the model was consulted but its ensemble spread exceeded 5 %
@@ -210,10 +238,12 @@ int qr_tune(int64_t M, int64_t N, int64_t batch, int *NB, int *IB, int *source);
 int qr_tune_units(int64_t M, int64_t N, int64_t batch, int *cus);
 
 /* Loads a decision table (host path; text: lines "entry M N batch NB IB
- * gflops [units]", where units is the compute-unit count the grid is sized
- * for, 0 or absent for all; optional "default NB IB"; '#' comments),
- * replacing the current one. Returns 0, TILEQR_ERR_NOTABLE, or -1 for a
- * null path. */
+ * gflops [units [p]]", where units is the compute-unit count the grid is
+ * sized for, 0 or absent for all, and p the row domains of qr_factor_ca
+ * (absent: 1); lines "budget C" start a section of entries tuned for
+ * callers limited to C compute units (0, the default: the whole device);
+ * optional "default NB IB"; '#' comments), replacing the current one.
+ * Returns 0, TILEQR_ERR_NOTABLE, or -1 for a null path. */
 int qr_tune_load(const char *path);
 
 /* Installs (or with nmodels = 0 removes) the ensemble of cost models used by
@@ -277,19 +307,22 @@ double qr_flops(int64_t M, int64_t N);
  * by task (for the IB overhead of Section 2.2). */
 double qr_flops_executed(int64_t M, int64_t N, int NB, int IB);
 
-/* Builds the ticket order (as qr_factor / qr_apply_Qt would, for `workers`
- * persistent workgroups; apply != 0 for qr_apply_Qt with nrhs columns) and
+/* Builds the ticket order (as qr_factor_ca / qr_apply_Qt_ca would with p row
+ * domains, for `workers` persistent workgroups; apply != 0 for the apply with
+ * nrhs columns) and
  * checks it on the host: *seq = waits not yet satisfied when tasks run one
  * at a time in ticket order; *stress = data hazards (program-order
  * violations) seen in a randomised parallel replay with `workers` workers
  * (seed), or -1 if that replay deadlocked. Returns 0 or a positive error. */
-int qr_plan_check(int64_t M, int64_t N, int NB, int IB, int64_t nrhs, int apply, int workers,
-                  uint64_t seed, int64_t *ntasks, int64_t *seq, int64_t *stress);
+int qr_plan_check(int64_t M, int64_t N, int NB, int IB, int p, int64_t nrhs, int apply,
+                  int workers, uint64_t seed, int64_t *ntasks, int64_t *seq, int64_t *stress);
 
 /* Writes the ticket order as 5 ints per task (type, i, j, k, strip) into
- * out (host, capacity cap tasks); *ntasks receives the count. */
-int qr_plan_tasks(int64_t M, int64_t N, int NB, int IB, int64_t nrhs, int apply, int workers,
-                  int32_t *out, int64_t cap, int64_t *ntasks);
+ * out (host, capacity cap tasks); *ntasks receives the count. Types: 0
+ * GEQRT, 1 TSQRT, 2 LARFB, 3 SSRFB, 4 LARFB on B, 5 SSRFB on B, 6 TTQRT
+ * (merge), 7 TTMQR (merge update), 8 TTMQR on B. */
+int qr_plan_tasks(int64_t M, int64_t N, int NB, int IB, int p, int64_t nrhs, int apply,
+                  int workers, int32_t *out, int64_t cap, int64_t *ntasks);
 
 #ifdef __cplusplus
 }

@@ -47,10 +47,11 @@ def colmajor(M, N, dtype=None, device="cuda", fill=None):
     return t
 
 
-def T_size(M, N, nb, ib):
-    n = _lib.lib().qr_T_size(M, N, nb, ib)
+def T_size(M, N, nb, ib, p=1):
+    """Doubles of the T buffer (qr_T_size_ca; p = 1: the flat tree's)."""
+    n = _lib.lib().qr_T_size_ca(M, N, nb, ib, p)
     if n < 0:
-        raise TileQRError("qr_T_size: invalid argument %d" % -n)
+        raise TileQRError("qr_T_size_ca: invalid argument %d" % -n)
     return n
 
 
@@ -110,6 +111,29 @@ def factor(A, nb=0, ib=0, T=None, stream=None):
     check(_lib.lib().qr_factor(ctypes.c_void_p(A.data_ptr()), M, N, _ld(A), nb, ib,
                                ctypes.c_void_p(T.data_ptr()), _stream(stream)), "qr_factor")
     return A, T, nb, ib
+
+
+def factor_ca(A, nb, ib, p, T=None, stream=None):
+    """qr_factor_ca: tile QR with p row domains merged over a binary tree
+    (p = 1: the flat tree). Returns (A, T)."""
+    torch = _torch()
+    M, N = A.shape
+    _ensure_table()
+    if T is None:
+        T = torch.empty(max(1, T_size(M, N, nb, ib, p)), dtype=torch.float64, device=A.device)
+    check(_lib.lib().qr_factor_ca(ctypes.c_void_p(A.data_ptr()), M, N, _ld(A), nb, ib, p,
+                                  ctypes.c_void_p(T.data_ptr()), _stream(stream)), "qr_factor_ca")
+    return A, T
+
+
+def apply_Qt_ca(A, T, nb, ib, p, B, stream=None):
+    """B <- Q^T B in place with Q from factor_ca (same nb, ib, p)."""
+    M, N = A.shape
+    _ensure_table()
+    check(_lib.lib().qr_apply_Qt_ca(ctypes.c_void_p(A.data_ptr()), M, N, _ld(A), nb, ib, p,
+                                    ctypes.c_void_p(T.data_ptr()), ctypes.c_void_p(B.data_ptr()),
+                                    B.shape[1], _ld(B), _stream(stream)), "qr_apply_Qt_ca")
+    return B
 
 
 def factor_noalloc(A, nb, ib, T, stream=None):
@@ -219,20 +243,20 @@ def dag_counts(M, N, nb):
     return list(c)
 
 
-def plan_check(M, N, nb, ib, nrhs=0, apply=False, workers=256, seed=0):
+def plan_check(M, N, nb, ib, nrhs=0, apply=False, workers=256, seed=0, p=1):
     nt, seq, stress = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-    check(_lib.lib().qr_plan_check(M, N, nb, ib, nrhs, int(apply), workers, seed, ctypes.byref(nt),
+    check(_lib.lib().qr_plan_check(M, N, nb, ib, p, nrhs, int(apply), workers, seed, ctypes.byref(nt),
                                    ctypes.byref(seq), ctypes.byref(stress)), "qr_plan_check")
     return nt.value, seq.value, stress.value
 
 
-def plan_tasks(M, N, nb, ib, nrhs=0, apply=False, workers=256):
+def plan_tasks(M, N, nb, ib, nrhs=0, apply=False, workers=256, p=1):
     import numpy as np
     nt = ctypes.c_int64()
-    check(_lib.lib().qr_plan_tasks(M, N, nb, ib, nrhs, int(apply), workers, None, 0, ctypes.byref(nt)),
-          "qr_plan_tasks")
+    check(_lib.lib().qr_plan_tasks(M, N, nb, ib, p, nrhs, int(apply), workers, None, 0,
+                                   ctypes.byref(nt)), "qr_plan_tasks")
     out = np.zeros((max(1, nt.value), 5), dtype=np.int32)
-    check(_lib.lib().qr_plan_tasks(M, N, nb, ib, nrhs, int(apply), workers,
+    check(_lib.lib().qr_plan_tasks(M, N, nb, ib, p, nrhs, int(apply), workers,
                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), nt.value,
                                    ctypes.byref(nt)), "qr_plan_tasks")
     return out[:nt.value]

@@ -28,6 +28,9 @@ c_fltp = ctypes.POINTER(ctypes.c_float)
 SIGNATURES = {
     "qr_version": (ctypes.c_char_p, []),
     "qr_T_size": (c_i64, [c_i64, c_i64, c_int, c_int]),
+    "qr_T_size_ca": (c_i64, [c_i64, c_i64, c_int, c_int, c_int]),
+    "qr_factor_ca": (c_int, [c_vp, c_i64, c_i64, c_i64, c_int, c_int, c_int, c_vp, c_vp]),
+    "qr_apply_Qt_ca": (c_int, [c_vp, c_i64, c_i64, c_i64, c_int, c_int, c_int, c_vp, c_vp, c_i64, c_i64, c_vp]),
     "qr_factor": (c_int, [c_vp, c_i64, c_i64, c_i64, c_int, c_int, c_vp, c_vp]),
     "qr_factor_noalloc": (c_int, [c_vp, c_i64, c_i64, c_i64, c_int, c_int, c_vp, c_vp]),
     "qr_apply_Qt": (c_int, [c_vp, c_i64, c_i64, c_i64, c_int, c_int, c_vp, c_vp, c_i64, c_i64, c_vp]),
@@ -49,8 +52,8 @@ SIGNATURES = {
     "qr_dag_counts": (c_int, [c_i64, c_i64, c_int, c_i64p]),
     "qr_flops": (c_dbl, [c_i64, c_i64]),
     "qr_flops_executed": (c_dbl, [c_i64, c_i64, c_int, c_int]),
-    "qr_plan_check": (c_int, [c_i64, c_i64, c_int, c_int, c_i64, c_int, c_int, c_u64, c_i64p, c_i64p, c_i64p]),
-    "qr_plan_tasks": (c_int, [c_i64, c_i64, c_int, c_int, c_i64, c_int, c_int, c_i32p, c_i64, c_i64p]),
+    "qr_plan_check": (c_int, [c_i64, c_i64, c_int, c_int, c_int, c_i64, c_int, c_int, c_u64, c_i64p, c_i64p, c_i64p]),
+    "qr_plan_tasks": (c_int, [c_i64, c_i64, c_int, c_int, c_int, c_i64, c_int, c_int, c_i32p, c_i64, c_i64p]),
 }
 
 

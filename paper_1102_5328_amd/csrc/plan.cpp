@@ -7,7 +7,7 @@
 #include <random>
 #include <unordered_map>
 
-void md_init(MatDesc &md, int64_t M, int64_t N, int nb, int ib, int w, int64_t nrhs) {
+void md_init(MatDesc &md, int64_t M, int64_t N, int nb, int ib, int w, int64_t nrhs, int p) {
   md.M = (int32_t)M;
   md.N = (int32_t)N;
   md.nb = nb;
@@ -20,27 +20,47 @@ void md_init(MatDesc &md, int64_t M, int64_t N, int nb, int ib, int w, int64_t n
   md.nrhs = (int32_t)nrhs;
   md.SB = nrhs > 0 ? (int32_t)((nrhs + w - 1) / w) : 0;
   md.gmax = 1;
+  const int pp = p < 1 ? 1 : (p > md.MT ? (md.MT > 0 ? md.MT : 1) : p);
+  md.h = md.MT > 0 ? (md.MT + pp - 1) / pp : 1;
+  md.D = md.MT > 0 ? (md.MT + md.h - 1) / md.h : 1;
+}
+
+void tree_step(const MatDesc &md, int k, std::vector<int> &heads, std::vector<int> &rest,
+               std::vector<int> &bottoms) {
+  heads.clear();
+  rest.clear();
+  bottoms.clear();
+  for (int i = k; i < md.MT; ++i) (tree_is_head(md, i, k) ? heads : rest).push_back(i);
+  const int dk = k / md.h, E = md.D - dk;
+  for (int l = 0; (1 << l) < E; ++l)
+    for (int e1 = 0; e1 + (1 << l) < E; e1 += 2 << l) bottoms.push_back((dk + e1 + (1 << l)) * md.h);
 }
 
 void enum_factor_tasks(const MatDesc &md, int mat, std::vector<Task> &out) {
+  std::vector<int> heads, rest, bottoms;
   for (int k = 0; k < md.KT; ++k) {
-    out.push_back(make_task(TK_GEQRT, mat, k, k, k, 0));
-    for (int i = k + 1; i < md.MT; ++i) out.push_back(make_task(TK_TSQRT, mat, i, k, k, 0));
-    for (int j = k + 1; j < md.NT; ++j)
-      for (int s = 0; s < strips_of(md, j); ++s)
-        out.push_back(make_task(TK_LARFB, mat, k, j, k, s));
-    for (int i = k + 1; i < md.MT; ++i)
-      for (int j = k + 1; j < md.NT; ++j)
-        for (int s = 0; s < strips_of(md, j); ++s)
-          out.push_back(make_task(TK_SSRFB, mat, i, j, k, s));
+    tree_step(md, k, heads, rest, bottoms);
+    for (int i : heads) out.push_back(make_task(TK_GEQRT, mat, i, k, k, 0));
+    for (int i : rest) out.push_back(make_task(TK_TSQRT, mat, i, k, k, 0));
+    for (int i : bottoms) out.push_back(make_task(TK_TTQRT, mat, i, k, k, 0));
+    const int types[3] = {TK_LARFB, TK_SSRFB, TK_TTMQR};
+    const std::vector<int> *rows[3] = {&heads, &rest, &bottoms};
+    for (int q = 0; q < 3; ++q)
+      for (int i : *rows[q])
+        for (int j = k + 1; j < md.NT; ++j)
+          for (int s = 0; s < strips_of(md, j); ++s) out.push_back(make_task(types[q], mat, i, j, k, s));
   }
 }
 
 void enum_apply_tasks(const MatDesc &md, int mat, std::vector<Task> &out) {
+  std::vector<int> heads, rest, bottoms;
   for (int k = 0; k < md.KT; ++k) {
-    for (int s = 0; s < md.SB; ++s) out.push_back(make_task(TK_LARFB_B, mat, k, 0, k, s));
-    for (int i = k + 1; i < md.MT; ++i)
-      for (int s = 0; s < md.SB; ++s) out.push_back(make_task(TK_SSRFB_B, mat, i, 0, k, s));
+    tree_step(md, k, heads, rest, bottoms);
+    const int types[3] = {TK_LARFB_B, TK_SSRFB_B, TK_TTMQR_B};
+    const std::vector<int> *rows[3] = {&heads, &rest, &bottoms};
+    for (int q = 0; q < 3; ++q)
+      for (int i : *rows[q])
+        for (int s = 0; s < md.SB; ++s) out.push_back(make_task(types[q], mat, i, 0, k, s));
   }
 }
 
@@ -67,40 +87,24 @@ double task_cost(const Task &t, const MatDesc &m) {
   const double l_fix = 48000.0, l_rate = 0.066;  // LARFB: ns + ns per (rows*refl*cols)
   const double s_fix = 94000.0, s_rate = 0.103;  // SSRFB
   int s = task_strip(t);
-  switch (task_type(t)) {
+  const int ty = task_type(t);
+  const double mb = tile_rows(m, t.i), nbk = tile_cols(m, t.k);
+  double c = task_on_B(ty) ? m.nrhs - s * m.w : (ty == TK_GEQRT || ty == TK_TSQRT || ty == TK_TTQRT)
+                                                      ? 0.0 : tile_cols(m, t.j) - s * m.w;
+  c = c < m.w ? c : m.w;
+  switch (ty) {
     case TK_GEQRT: {
-      double mb = tile_rows(m, t.k), nb = tile_cols(m, t.k);
-      double kk = mb < nb ? mb : nb;
+      double kk = mb < nbk ? mb : nbk;
       return kk * (g_col0 + g_row * mb);
     }
-    case TK_TSQRT: {
-      double mb = tile_rows(m, t.i), nb = tile_cols(m, t.k);
-      return nb * (t_col0 + t_row * mb);
-    }
-    case TK_LARFB: {
-      double mb = tile_rows(m, t.k), nb = tile_cols(m, t.k);
-      double c = tile_cols(m, t.j) - s * m.w;
-      c = c < m.w ? c : m.w;
-      return l_fix + l_rate * mb * nb * c;
-    }
-    case TK_SSRFB: {
-      double mb = tile_rows(m, t.i), nb = tile_cols(m, t.k);
-      double c = tile_cols(m, t.j) - s * m.w;
-      c = c < m.w ? c : m.w;
-      return s_fix + s_rate * mb * nb * c;
-    }
-    case TK_LARFB_B: {
-      double mb = tile_rows(m, t.k), nb = tile_cols(m, t.k);
-      double c = m.nrhs - s * m.w;
-      c = c < m.w ? c : m.w;
-      return l_fix + l_rate * mb * nb * c;
-    }
-    case TK_SSRFB_B: {
-      double mb = tile_rows(m, t.i), nb = tile_cols(m, t.k);
-      double c = m.nrhs - s * m.w;
-      c = c < m.w ? c : m.w;
-      return s_fix + s_rate * mb * nb * c;
-    }
+    case TK_TSQRT:
+    case TK_TTQRT: return nbk * (t_col0 + t_row * mb);
+    case TK_LARFB:
+    case TK_LARFB_B: return l_fix + l_rate * mb * nbk * c;
+    case TK_SSRFB:
+    case TK_TTMQR:
+    case TK_SSRFB_B:
+    case TK_TTMQR_B: return s_fix + s_rate * mb * nbk * c;
   }
   return 1.0;
 }
@@ -252,8 +256,8 @@ int64_t check_order_sequential(const std::vector<MatDesc> &mats, const std::vect
 namespace {
 
 // Data items a task touches, written from what each kernel reads and writes
-// (independently of the counter protocol). The diagonal tile is split into
-// its R part (upper, rewritten by every TSQRT of the step) and its V part
+// (independently of the counter protocol). A head tile is split into its R
+// part (upper, rewritten by the TSQRTs and merges of the step) and its V part
 // (lower, read by the LARFBs of the step).
 struct Access {
   int64_t item;
@@ -263,14 +267,18 @@ struct Access {
 int64_t item_strip(const MatDesc &m, int mat, int i, int j, int s) {
   return ((int64_t)mat << 40) | ((((int64_t)i * m.NT + j) * m.S + s) * 4 + 0);
 }
-int64_t item_rpart(const MatDesc &m, int mat, int k) {
-  return ((int64_t)mat << 40) | ((((int64_t)k * m.NT + k) * m.S) * 4 + 1);
+int64_t item_rpart(const MatDesc &m, int mat, int i, int k) {
+  return ((int64_t)mat << 40) | ((((int64_t)i * m.NT + k) * m.S) * 4 + 1);
 }
-int64_t item_vpart(const MatDesc &m, int mat, int k) {
-  return ((int64_t)mat << 40) | ((((int64_t)k * m.NT + k) * m.S) * 4 + 2);
+int64_t item_vpart(const MatDesc &m, int mat, int i, int k) {
+  return ((int64_t)mat << 40) | ((((int64_t)i * m.NT + k) * m.S) * 4 + 2);
 }
 int64_t item_T(const MatDesc &m, int mat, int i, int k) {
   return ((int64_t)mat << 40) | ((((int64_t)i * m.NT + k) * m.S) * 4 + 3);
+}
+// A merge's reflector block and T factor (domain d of the bottom head, step k).
+int64_t item_tree(const MatDesc &m, int mat, int d, int k, int which) {
+  return ((int64_t)mat << 40) | ((int64_t)1 << 38) | ((((int64_t)k * m.D + d) << 1) + which);
 }
 int64_t item_B(const MatDesc &m, int mat, int i, int s) {
   return ((int64_t)mat << 40) | ((int64_t)1 << 39) | ((int64_t)i * m.SB + s);
@@ -281,32 +289,48 @@ void accesses(const Task &t, const MatDesc &m, std::vector<Access> &a) {
   int mat = task_mat(t), i = t.i, j = t.j, k = t.k, s = task_strip(t);
   switch (task_type(t)) {
     case TK_GEQRT:
-      for (int q = 0; q < strips_of(m, k); ++q) a.push_back({item_strip(m, mat, k, k, q), true});
-      a.push_back({item_rpart(m, mat, k), true});
-      a.push_back({item_vpart(m, mat, k), true});
-      a.push_back({item_T(m, mat, k, k), true});
+      for (int q = 0; q < strips_of(m, k); ++q) a.push_back({item_strip(m, mat, i, k, q), true});
+      a.push_back({item_rpart(m, mat, i, k), true});
+      a.push_back({item_vpart(m, mat, i, k), true});
+      a.push_back({item_T(m, mat, i, k), true});
       break;
     case TK_TSQRT:
-      a.push_back({item_rpart(m, mat, k), true});
+      a.push_back({item_rpart(m, mat, tree_head(m, i, k), k), true});
       for (int q = 0; q < strips_of(m, k); ++q) a.push_back({item_strip(m, mat, i, k, q), true});
       a.push_back({item_T(m, mat, i, k), true});
       break;
+    case TK_TTQRT:
+      a.push_back({item_rpart(m, mat, tree_partner(m, i, k), k), true});
+      a.push_back({item_rpart(m, mat, i, k), false});
+      a.push_back({item_tree(m, mat, i / m.h, k, 0), true});
+      a.push_back({item_tree(m, mat, i / m.h, k, 1), true});
+      break;
     case TK_LARFB:
-      a.push_back({item_vpart(m, mat, k), false});
-      a.push_back({item_T(m, mat, k, k), false});
-      a.push_back({item_strip(m, mat, k, j, s), true});
+      a.push_back({item_vpart(m, mat, i, k), false});
+      a.push_back({item_T(m, mat, i, k), false});
+      a.push_back({item_strip(m, mat, i, j, s), true});
       break;
     case TK_SSRFB:
       for (int q = 0; q < strips_of(m, k); ++q) a.push_back({item_strip(m, mat, i, k, q), false});
       a.push_back({item_T(m, mat, i, k), false});
-      a.push_back({item_strip(m, mat, k, j, s), true});
+      a.push_back({item_strip(m, mat, tree_head(m, i, k), j, s), true});
+      a.push_back({item_strip(m, mat, i, j, s), true});
+      break;
+    case TK_TTMQR:
+      a.push_back({item_tree(m, mat, i / m.h, k, 0), false});
+      a.push_back({item_tree(m, mat, i / m.h, k, 1), false});
+      a.push_back({item_strip(m, mat, tree_partner(m, i, k), j, s), true});
       a.push_back({item_strip(m, mat, i, j, s), true});
       break;
     case TK_LARFB_B:
-      a.push_back({item_B(m, mat, k, s), true});
+      a.push_back({item_B(m, mat, i, s), true});
       break;
     case TK_SSRFB_B:
-      a.push_back({item_B(m, mat, k, s), true});
+      a.push_back({item_B(m, mat, tree_head(m, i, k), s), true});
+      a.push_back({item_B(m, mat, i, s), true});
+      break;
+    case TK_TTMQR_B:
+      a.push_back({item_B(m, mat, tree_partner(m, i, k), s), true});
       a.push_back({item_B(m, mat, i, s), true});
       break;
   }

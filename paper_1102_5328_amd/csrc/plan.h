@@ -7,12 +7,19 @@
 
 #include "tq_sched.h"
 
-// Fills the geometry fields of a descriptor (pointers untouched).
-void md_init(MatDesc &md, int64_t M, int64_t N, int nb, int ib, int w, int64_t nrhs);
+// Fills the geometry fields of a descriptor (pointers untouched); p: number
+// of row domains of the reduction tree (1: flat tree; clamped to [1, MT]).
+void md_init(MatDesc &md, int64_t M, int64_t N, int nb, int ib, int w, int64_t nrhs, int p = 1);
+
+// Rows of step k: the heads (GEQRT), the other rows (TSQRT), and the bottom
+// heads of the merges in level order (TTQRT).
+void tree_step(const MatDesc &md, int k, std::vector<int> &heads, std::vector<int> &rest,
+               std::vector<int> &bottoms);
 
 // Tasks of one matrix in the sequential program order of the tile algorithm
-// (step k ascending; within a step GEQRT, the TSQRT chain, the LARFBs, then
-// the SSRFBs with i ascending). This order is a topological order of the DAG.
+// (step k ascending; within a step the GEQRTs, the TSQRTs with i ascending,
+// the merges in level order, then the LARFBs, SSRFBs and TTMQRs in the same
+// row orders). This order is a topological order of the DAG.
 void enum_factor_tasks(const MatDesc &md, int mat, std::vector<Task> &out);
 void enum_apply_tasks(const MatDesc &md, int mat, std::vector<Task> &out);
 

@@ -35,6 +35,10 @@ struct DevState {
   long long wall_khz = 100000;
   int *err = nullptr;  // sticky device error word
 };
+// Compute units of the device (taken from the device when its state is set
+// up; the decision table's "all" budget stands for this count).
+int g_full_cus = 256;
+
 DevState g_dev[64];
 
 int dev_state(DevState **out) {
@@ -47,6 +51,7 @@ int dev_state(DevState **out) {
     if (hipGetDeviceProperties(&prop, d) != hipSuccess) return TILEQR_ERR_NODEVICE;
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return TILEQR_ERR_NODEVICE;
     s.ncu = prop.multiProcessorCount;
+    g_full_cus = s.ncu;
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, d) == hipSuccess && khz > 0)
       s.wall_khz = khz;
@@ -104,9 +109,10 @@ struct PlanKey {
   int64_t M, N, nrhs;
   uint64_t batch_hash;
   int cus = g_cu_limit;
+  int h = 0;  // tile rows per domain of the reduction tree
   bool operator<(const PlanKey &o) const {
-    return std::tie(dev, apply, nb, ib, M, N, nrhs, batch_hash, cus) <
-           std::tie(o.dev, o.apply, o.nb, o.ib, o.M, o.N, o.nrhs, o.batch_hash, o.cus);
+    return std::tie(dev, apply, nb, ib, M, N, nrhs, batch_hash, cus, h) <
+           std::tie(o.dev, o.apply, o.nb, o.ib, o.M, o.N, o.nrhs, o.batch_hash, o.cus, o.h);
   }
   bool operator==(const PlanKey &o) const { return !(*this < o) && !(o < *this); }
 };
@@ -131,9 +137,9 @@ void touch(const PlanKey &k) {
 }
 
 // Geometry of one matrix: strip width and staged V chunks.
-void md_setup(MatDesc &md, int64_t M, int64_t N, int nb, int ib, int64_t nrhs) {
+void md_setup(MatDesc &md, int64_t M, int64_t N, int nb, int ib, int64_t nrhs, int p = 1) {
   const LdsPlan lp = lds_plan(nb, ib);
-  md_init(md, M, N, nb, ib, strip_width(nb), nrhs);
+  md_init(md, M, N, nb, ib, strip_width(nb), nrhs, p);
   md.gmax = lp.gmax;
 }
 
@@ -172,10 +178,14 @@ int get_plan(const PlanKey &key, std::vector<MatDesc> mats, bool apply, const De
   // Host-side bounds check of every task against its matrix's tiling.
   for (const Task &t : order) {
     const MatDesc &m = mats[task_mat(t)];
-    bool ok = t.k >= 0 && t.k < m.KT && t.i >= 0 && t.i < m.MT && t.j >= 0 && t.j < m.NT;
-    int s = task_strip(t);
-    if (task_type(t) == TK_LARFB || task_type(t) == TK_SSRFB) ok = ok && s < strips_of(m, t.j);
-    if (task_type(t) >= TK_LARFB_B) ok = ok && s < m.SB;
+    bool ok = t.k >= 0 && t.k < m.KT && t.i >= t.k && t.i < m.MT && t.j >= 0 && t.j < m.NT;
+    const int s = task_strip(t), ty = task_type(t);
+    if (ty == TK_LARFB || ty == TK_SSRFB || ty == TK_TTMQR) ok = ok && t.j > t.k && s < strips_of(m, t.j);
+    if (task_on_B(ty)) ok = ok && s < m.SB;
+    if (ty == TK_GEQRT || ty == TK_LARFB || ty == TK_LARFB_B) ok = ok && tree_is_head(m, t.i, t.k);
+    if (ty == TK_TSQRT || ty == TK_SSRFB || ty == TK_SSRFB_B) ok = ok && !tree_is_head(m, t.i, t.k);
+    if (ty == TK_TTQRT || ty == TK_TTMQR || ty == TK_TTMQR_B)
+      ok = ok && t.i % m.h == 0 && t.i / m.h > t.k / m.h;
     if (!ok) {
       delete p;
       return TILEQR_ERR_INTERNAL;
@@ -280,30 +290,32 @@ int resolve_tiling(int64_t M, int64_t N, int64_t batch, int *nb, int *ib) {
 }
 
 int units_for(int64_t M, int64_t N, int64_t batch);
+int domains_for(int64_t M, int64_t N, int nb);
 
-int factor_one(double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, double *T,
+int factor_one(double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, int p, double *T,
                hipStream_t st, const DevState &ds) {
   if (M == 0 || N == 0) return 0;
   MatDesc md;
   std::memset(&md, 0, sizeof(md));
-  md_setup(md, M, N, NB, IB, 0);
+  md_setup(md, M, N, NB, IB, 0, p);
   md.lda = lda;
   PlanKey key{0, 0, NB, IB, M, N, 0, 0};
   key.cus = units_for(M, N, 1);
+  key.h = md.h;
   hipGetDevice(&key.dev);
-  Plan *p = nullptr;
-  int rc = get_plan(key, {md}, false, ds, &p);
+  Plan *pl = nullptr;
+  int rc = get_plan(key, {md}, false, ds, &pl);
   if (rc) return rc;
   md.A = A;
   md.T = T;
   md.B = nullptr;
   md.ctr = 0;
-  TqLaunch a = make_launch(*p, ds, md);
+  TqLaunch a = make_launch(*pl, ds, md);
   if (trace_on()) {
-    a.trace = trace_buffer(p->ntasks);
-    g_trace.order.resize(p->ntasks);
-    if (p->ntasks)
-      hipMemcpy(g_trace.order.data(), p->d_tasks, sizeof(Task) * p->ntasks, hipMemcpyDeviceToHost);
+    a.trace = trace_buffer(pl->ntasks);
+    g_trace.order.resize(pl->ntasks);
+    if (pl->ntasks)
+      hipMemcpy(g_trace.order.data(), pl->d_tasks, sizeof(Task) * pl->ntasks, hipMemcpyDeviceToHost);
   }
   if (tq_launch_persistent(a, st) != hipSuccess) return TILEQR_ERR_HIP;
   return 0;
@@ -320,20 +332,42 @@ struct TableEntry {
   int64_t M, N, batch;
   int nb, ib;
   double gflops;
-  int cus;  // compute units the grid is sized for (0: all)
+  int cus;     // compute units the grid is sized for (0: all)
+  int p;       // row domains of the reduction tree (1: flat tree)
+  int budget;  // compute units of the callers the entry was tuned for (0: all)
 };
 std::vector<TableEntry> g_table;
 int g_default_nb = 128, g_default_ib = 32;
 
 // Nearest benchmarked configuration (Section 6.1): log M, log N, log batch;
 // ties go to the larger configuration. nullptr when the table is empty.
+// Budget of the table section that serves callers limited to `cus` compute
+// units (0: the whole device): the nearest in log scale (Section 6.1's
+// interpolation over the core count); -1 when the table is empty.
+int table_budget(int cus) {
+  const double want = std::log((double)(cus > 0 ? cus : g_full_cus));
+  int best = -1;
+  double bd = 1e300;
+  for (const TableEntry &e : g_table) {
+    const int eff = e.budget > 0 ? e.budget : g_full_cus;
+    const double d = std::fabs(std::log((double)eff) - want);
+    if (d < bd - 1e-12 || (std::fabs(d - bd) <= 1e-12 && e.budget == 0)) {
+      bd = d;
+      best = e.budget;
+    }
+  }
+  return best;
+}
+
 const TableEntry *nearest_entry(int64_t M, int64_t N, int64_t batch) {
   const double lm = std::log((double)std::max<int64_t>(M, 1)),
                ln = std::log((double)std::max<int64_t>(N, 1)), lb = std::log((double)batch);
+  const int budget = table_budget(g_cu_limit);
   const TableEntry *best = nullptr;
   double bd = 1e300;
   int64_t bsize = -1;
   for (const TableEntry &e : g_table) {
+    if (e.budget != budget) continue;
     const double d = std::pow(std::log((double)e.M) - lm, 2) +
                      std::pow(std::log((double)e.N) - ln, 2) +
                      std::pow(std::log((double)e.batch) - lb, 2);
@@ -355,6 +389,14 @@ int units_for(int64_t M, int64_t N, int64_t batch) {
   return e ? e->cus : 0;
 }
 
+// Row domains of the reduction tree for one matrix: the nearest entry's
+// (tuned with its tile order; 1 without a table).
+int domains_for(int64_t M, int64_t N, int nb) {
+  (void)nb;
+  const TableEntry *e = nearest_entry(M, N, 1);
+  return e && e->p > 0 ? e->p : 1;
+}
+
 struct ModelState {
   int nmodels = 0;
   std::vector<float> params;
@@ -374,34 +416,49 @@ extern "C" {
 
 const char *qr_version(void) { return "tileqr 0.1 (gfx950, FP64 MFMA)"; }
 
-int64_t qr_T_size(int64_t M, int64_t N, int NB, int IB) {
+int64_t qr_T_size_ca(int64_t M, int64_t N, int NB, int IB, int p) {
   if (M < 0) return -1;
   if (N < 0) return -2;
   if (!nb_ok(NB)) return -3;
   if (IB < 1 || IB > NB) return -4;
-  int64_t MT = (M + NB - 1) / NB, NT = (N + NB - 1) / NB, KT = std::min(MT, NT);
-  return KT * MT * (int64_t)IB * NB;
+  if (p < 0) return -5;
+  if (M > INT32_MAX || N > INT32_MAX) return -1;
+  if (p == 0) p = domains_for(M, N, NB);
+  MatDesc md;
+  std::memset(&md, 0, sizeof(md));
+  md_init(md, M, N, NB, IB, strip_width(NB), 0, p);
+  return T_doubles(md);
 }
 
-int qr_factor(double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, double *T,
-              void *stream) {
+int64_t qr_T_size(int64_t M, int64_t N, int NB, int IB) { return qr_T_size_ca(M, N, NB, IB, 1); }
+
+int qr_factor_ca(double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, int p, double *T,
+                 void *stream) {
   if (M < 0) return -2;
   if (N < 0) return -3;
   if (!A && M * N > 0) return -1;
   if (lda < std::max<int64_t>(1, M)) return -4;
   if (NB != 0 && !nb_ok(NB)) return -5;
   if (IB < 0 || (NB != 0 && IB > NB)) return -6;
+  if (p < 0) return -7;
   if (M > INT32_MAX || N > INT32_MAX) return TILEQR_ERR_TOO_LARGE;
   int rc = resolve_tiling(M, N, 1, &NB, &IB);
   if (rc) return rc;
   if (!nb_ok(NB)) return -5;
   if (IB < 1 || IB > NB) return -6;
-  if (!T && M * N > 0) return -7;
+  if (!T && M * N > 0) return -8;
   if (!nb_enabled(NB)) return TILEQR_ERR_DISABLED;
+  if (p == 0) p = domains_for(M, N, NB);
   std::lock_guard<std::mutex> lk(g_mu);
   DevState *ds;
   if ((rc = dev_state(&ds))) return rc;
-  return factor_one(A, M, N, lda, NB, IB, T, (hipStream_t)stream, *ds);
+  return factor_one(A, M, N, lda, NB, IB, p, T, (hipStream_t)stream, *ds);
+}
+
+int qr_factor(double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, double *T,
+              void *stream) {
+  const int rc = qr_factor_ca(A, M, N, lda, NB, IB, 1, T, stream);
+  return rc == -8 ? -7 : rc;
 }
 
 int qr_factor_noalloc(double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, double *T,
@@ -466,46 +523,55 @@ int qr_factor_noalloc(double *A, int64_t M, int64_t N, int64_t lda, int NB, int 
   return 0;
 }
 
-int qr_apply_Qt(const double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB,
-                const double *T, double *B, int64_t nrhs, int64_t ldb, void *stream) {
+int qr_apply_Qt_ca(const double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, int p,
+                   const double *T, double *B, int64_t nrhs, int64_t ldb, void *stream) {
   if (M < 0) return -2;
   if (N < 0) return -3;
   if (!A && M * N > 0) return -1;
   if (lda < std::max<int64_t>(1, M)) return -4;
   if (NB != 0 && !nb_ok(NB)) return -5;
   if (IB < 0 || (NB != 0 && IB > NB)) return -6;
+  if (p < 0) return -7;
   int rc = resolve_tiling(M, N, 1, &NB, &IB);
   if (rc) return rc;
   if (!nb_ok(NB)) return -5;
   if (IB < 1 || IB > NB) return -6;
-  if (!T && M * N > 0) return -7;
-  if (nrhs < 0) return -9;
-  if (!B && M * nrhs > 0) return -8;
-  if (ldb < std::max<int64_t>(1, M)) return -10;
+  if (!T && M * N > 0) return -8;
+  if (nrhs < 0) return -10;
+  if (!B && M * nrhs > 0) return -9;
+  if (ldb < std::max<int64_t>(1, M)) return -11;
   if (M > INT32_MAX || N > INT32_MAX || nrhs > INT32_MAX) return TILEQR_ERR_TOO_LARGE;
   if (!nb_enabled(NB)) return TILEQR_ERR_DISABLED;
   if (M == 0 || N == 0 || nrhs == 0) return 0;
+  if (p == 0) p = domains_for(M, N, NB);
   std::lock_guard<std::mutex> lk(g_mu);
   DevState *ds;
   if ((rc = dev_state(&ds))) return rc;
   MatDesc md;
   std::memset(&md, 0, sizeof(md));
-  md_setup(md, M, N, NB, IB, nrhs);
+  md_setup(md, M, N, NB, IB, nrhs, p);
   if ((int64_t)md.SB > 4095) return TILEQR_ERR_TOO_LARGE;
   md.lda = lda;
   md.ldb = ldb;
   PlanKey key{0, 1, NB, IB, M, N, nrhs, 0};
   key.cus = units_for(M, N, 1);
+  key.h = md.h;
   hipGetDevice(&key.dev);
-  Plan *p = nullptr;
-  if ((rc = get_plan(key, {md}, true, *ds, &p))) return rc;
+  Plan *pl = nullptr;
+  if ((rc = get_plan(key, {md}, true, *ds, &pl))) return rc;
   md.A = const_cast<double *>(A);
   md.T = const_cast<double *>(T);
   md.B = B;
   md.ctr = 0;
-  TqLaunch a = make_launch(*p, *ds, md);
+  TqLaunch a = make_launch(*pl, *ds, md);
   if (tq_launch_persistent(a, (hipStream_t)stream) != hipSuccess) return TILEQR_ERR_HIP;
   return 0;
+}
+
+int qr_apply_Qt(const double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB,
+                const double *T, double *B, int64_t nrhs, int64_t ldb, void *stream) {
+  const int rc = qr_apply_Qt_ca(A, M, N, lda, NB, IB, 1, T, B, nrhs, ldb, stream);
+  return rc <= -8 ? rc + 1 : rc;  // the argument positions without p
 }
 
 static int batched_check(double *const *A, const int64_t *M, const int64_t *N, const int64_t *lda,
@@ -609,7 +675,7 @@ int qr_factor_loop(double *const *A, const int64_t *M, const int64_t *N, const i
   DevState *ds;
   if ((rc = dev_state(&ds))) return rc;
   for (int64_t b = 0; b < count; ++b) {
-    rc = factor_one(A[b], M[b], N[b], lda[b], nbs[b], ibs[b], T[b], (hipStream_t)stream, *ds);
+    rc = factor_one(A[b], M[b], N[b], lda[b], nbs[b], ibs[b], 1, T[b], (hipStream_t)stream, *ds);
     if (rc) return rc;
   }
   return 0;
@@ -835,7 +901,7 @@ int qr_tune_load(const char *path) {
   FILE *f = std::fopen(path, "r");
   if (!f) return TILEQR_ERR_NOTABLE;
   std::vector<TableEntry> t;
-  int dnb = 128, dib = 32;
+  int dnb = 128, dib = 32, budget = 0;
   char line[512];
   bool bad = false;
   while (std::fgets(line, sizeof line, f)) {
@@ -845,15 +911,19 @@ int qr_tune_load(const char *path) {
     TableEntry e;
     long long m, n, b;
     e.cus = 0;
-    const int got = std::sscanf(p, "entry %lld %lld %lld %d %d %lf %d", &m, &n, &b, &e.nb, &e.ib,
-                                &e.gflops, &e.cus);
-    if (got == 6 || got == 7) {
-      if (e.cus < 0) bad = true;
+    e.p = 1;
+    e.budget = budget;
+    const int got = std::sscanf(p, "entry %lld %lld %lld %d %d %lf %d %d", &m, &n, &b, &e.nb,
+                                &e.ib, &e.gflops, &e.cus, &e.p);
+    if (got >= 6 && got <= 8) {
+      if (e.cus < 0 || e.p < 1) bad = true;
       e.M = m;
       e.N = n;
       e.batch = b;
       if (!nb_ok(e.nb) || e.ib < 1 || e.ib > e.nb || m < 1 || n < 1 || b < 1) bad = true;
       t.push_back(e);
+    } else if (std::sscanf(p, "budget %d", &budget) == 1) {
+      if (budget < 0) bad = true;
     } else if (std::sscanf(p, "default %d %d", &dnb, &dib) == 2) {
       if (!nb_ok(dnb) || dib < 1 || dib > dnb) bad = true;
     } else {
@@ -1034,12 +1104,13 @@ double qr_flops_executed(int64_t M, int64_t N, int NB, int IB) {
   return f;
 }
 
-int qr_plan_check(int64_t M, int64_t N, int NB, int IB, int64_t nrhs, int apply, int workers,
-                  uint64_t seed, int64_t *ntasks, int64_t *seq, int64_t *stress) {
-  if (M < 1 || N < 1 || !nb_ok(NB) || IB < 1 || IB > NB || workers < 1) return TILEQR_ERR_INTERNAL;
+int qr_plan_check(int64_t M, int64_t N, int NB, int IB, int p, int64_t nrhs, int apply,
+                  int workers, uint64_t seed, int64_t *ntasks, int64_t *seq, int64_t *stress) {
+  if (M < 1 || N < 1 || !nb_ok(NB) || IB < 1 || IB > NB || workers < 1 || p < 1)
+    return TILEQR_ERR_INTERNAL;
   MatDesc md;
   std::memset(&md, 0, sizeof(md));
-  md_setup(md, M, N, NB, IB, apply ? nrhs : 0);
+  md_setup(md, M, N, NB, IB, apply ? nrhs : 0, p);
   md.ctr = 0;
   std::vector<MatDesc> mats{md};
   std::vector<Task> order;
@@ -1051,12 +1122,13 @@ int qr_plan_check(int64_t M, int64_t N, int NB, int IB, int64_t nrhs, int apply,
   return 0;
 }
 
-int qr_plan_tasks(int64_t M, int64_t N, int NB, int IB, int64_t nrhs, int apply, int workers,
-                  int32_t *out, int64_t cap, int64_t *ntasks) {
-  if (M < 1 || N < 1 || !nb_ok(NB) || IB < 1 || IB > NB || workers < 1) return TILEQR_ERR_INTERNAL;
+int qr_plan_tasks(int64_t M, int64_t N, int NB, int IB, int p, int64_t nrhs, int apply,
+                  int workers, int32_t *out, int64_t cap, int64_t *ntasks) {
+  if (M < 1 || N < 1 || !nb_ok(NB) || IB < 1 || IB > NB || workers < 1 || p < 1)
+    return TILEQR_ERR_INTERNAL;
   MatDesc md;
   std::memset(&md, 0, sizeof(md));
-  md_setup(md, M, N, NB, IB, apply ? nrhs : 0);
+  md_setup(md, M, N, NB, IB, apply ? nrhs : 0, p);
   md.ctr = 0;
   std::vector<MatDesc> mats{md};
   std::vector<Task> order;

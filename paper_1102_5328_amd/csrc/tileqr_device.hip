@@ -979,21 +979,20 @@ __device__ inline void panel_T(const Lds &L, int pw, int ib) {
   }
 }
 
-// GEQRT(k) (ts = false): QR of the diagonal tile in place.
-// TSQRT(i, k) (ts = true): QR of [R_kk; A_ik]: R_kk updated in place, A_ik
-// overwritten by the lower parts of the reflectors [e_j; u_j].
+// ts = false (GEQRT): QR in place of the mrows x ncol block X (= R).
+// ts = true (TSQRT, and the merges): QR of [R; X] with R the upper triangle
+// of an ncol x ncol block of A (updated in place) and X an mrows x ncol block
+// (leading dimension ldx) overwritten by the lower parts of the reflectors
+// [e_j; u_j]. The block factors T go to Tp (ib x ncol).
 // Columns are taken in register panels of at most P = 16 * (4 / RW) columns
 // that never straddle an IB block unless IB > P.
 template <int RW>
-__device__ __forceinline__ void panel_task(const MatDesc &m, const Lds &L, bool ts, int i, int k) {
+__device__ __forceinline__ void panel_task(const MatDesc &m, const Lds &L, bool ts, double *R,
+                                           double *X, int64_t ldx, double *Tp, int mrows,
+                                           int ncol) {
   constexpr int ROWS = Geo<RW>::ROWS, P = Geo<RW>::P, ld = P + 1;
-  const int nb = m.nb, ib = m.ib;
+  const int ib = m.ib;
   const int64_t lda = m.lda;
-  double *R = m.A + (int64_t)k * nb * lda + (int64_t)k * nb;
-  double *X = ts ? m.A + (int64_t)k * nb * lda + (int64_t)i * nb : R;
-  double *Tp = m.T + ((int64_t)k * m.MT + (ts ? i : k)) * (int64_t)ib * nb;
-  const int mrows = ts ? tile_rows(m, i) : tile_rows(m, k);
-  const int ncol = tile_cols(m, k);
   const int K = ts ? ncol : min(mrows, ncol);
   const int ln = lane_id(), wv = wave_id();
   const int cg = wv / RW, rb = wv % RW, rbase = rb * TQ_ROWS_PER_WAVE;
@@ -1010,7 +1009,7 @@ __device__ __forceinline__ void panel_task(const MatDesc &m, const Lds &L, bool 
     pw = ib <= P ? min(K - c0, (P / ib) * ib) : min(P, min(sg + ib, K) - c0);
     const bool colok = mc < pw;
     d4 x[RT];
-    load_c2<true>(x, X + (int64_t)c0 * lda, lda, mrows, min(mc, pw - 1), colok, rbase);
+    load_c2<true>(x, X + (int64_t)c0 * ldx, ldx, mrows, min(mc, pw - 1), colok, rbase);
     if (ts) {
       for (int e = tid_x(); e < P * P; e += NTHR) {
         const int a = e / P, c = e % P;
@@ -1140,7 +1139,7 @@ __device__ __forceinline__ void panel_task(const MatDesc &m, const Lds &L, bool 
     __syncthreads();
     panel_T<RW>(L, pw, ib);
     // --- write back the panel: R above, reflectors below ---
-    store_c2<true>(x, X + (int64_t)c0 * lda, lda, mrows, mc, colok, rbase);
+    store_c2<true>(x, X + (int64_t)c0 * ldx, ldx, mrows, mc, colok, rbase);
     __syncthreads();
     if (ts) {
       for (int e = tid_x(); e < pw * pw; e += NTHR) {
@@ -1170,21 +1169,21 @@ __device__ __forceinline__ void panel_task(const MatDesc &m, const Lds &L, bool 
     // --- the rest of the tile: trailing columns [c0 + pw, ncol) ---
     const int rest = ncol - c0 - pw;
     if (rest > 0) {
-      const double *Vp = ts ? X + (int64_t)c0 * lda : X + c0 + (int64_t)c0 * lda;
+      const double *Vp = ts ? X + (int64_t)c0 * ldx : X + c0 + (int64_t)c0 * ldx;
       const int vrows = ts ? mrows : mrows - c0;
       double *C1 = ts ? R + c0 + (int64_t)(c0 + pw) * lda : nullptr;
-      double *C2 = ts ? X + (int64_t)(c0 + pw) * lda : X + c0 + (int64_t)(c0 + pw) * lda;
+      double *C2 = ts ? X + (int64_t)(c0 + pw) * ldx : X + c0 + (int64_t)(c0 + pw) * ldx;
       const double *Ta = ib <= P ? Tp + (int64_t)c0 * ib : Tp + (c0 - sg) + (int64_t)c0 * ib;
-      apply_cols<RW>(L, Vp, lda, vrows, ts ? VK_FULL : VK_UNIT, pw, ib <= P ? ib : pw, Ta, ib, C1, lda,
-                 C2, lda, rest);
+      apply_cols<RW>(L, Vp, ldx, vrows, ts ? VK_FULL : VK_UNIT, pw, ib <= P ? ib : pw, Ta, ib, C1, lda,
+                 C2, ldx, rest);
     }
   }
   if (ib > P) {
     for (int sg = 0; sg < K; sg += ib) {
       const int bw = min(ib, K - sg);
       if (bw <= P) continue;
-      const double *Vb = ts ? X + (int64_t)sg * lda : X + sg + (int64_t)sg * lda;
-      assemble_wide_T<RW>(L, Vb, lda, ts ? mrows : mrows - sg, ts ? VK_FULL : VK_UNIT, bw,
+      const double *Vb = ts ? X + (int64_t)sg * ldx : X + sg + (int64_t)sg * ldx;
+      assemble_wide_T<RW>(L, Vb, ldx, ts ? mrows : mrows - sg, ts ? VK_FULL : VK_UNIT, bw,
                       Tp + (int64_t)sg * ib, ib);
     }
   }
@@ -1199,35 +1198,55 @@ __device__ __forceinline__ void run_task(const Task &t, const MatDesc &m, const 
   const int nb = m.nb, ib = m.ib;
   const int i = t.i, j = t.j, k = t.k, strip = task_strip(t);
   const int type = task_type(t);
-  if (type == TK_GEQRT || type == TK_TSQRT) {
+  const int64_t lda = m.lda;
+  auto At = [&](int r, int c) { return m.A + (int64_t)c * nb * lda + (int64_t)r * nb; };
+  auto Tt = [&](int r, int c) { return m.T + ((int64_t)c * m.MT + r) * (int64_t)ib * nb; };
+  if (type == TK_GEQRT || type == TK_TSQRT || type == TK_TTQRT) {
     // Panels are the critical path: their waves win instruction issue over
     // co-resident update waves.
     __builtin_amdgcn_s_setprio(2);
-    panel_task<RW>(m, L, type == TK_TSQRT, i, k);
+    const int mrows = tile_rows(m, i), ncol = tile_cols(m, k);
+    if (type == TK_GEQRT) {
+      panel_task<RW>(m, L, false, At(i, k), At(i, k), lda, Tt(i, k), mrows, ncol);
+    } else if (type == TK_TSQRT) {
+      panel_task<RW>(m, L, true, At(tree_head(m, i, k), k), At(i, k), lda, Tt(i, k), mrows, ncol);
+    } else {
+      // merge: the bottom head's triangle (zeros below it) into its own
+      // block, then the TSQRT of [R_top; block]
+      double *Vt = m.T + tree_V_offset(m, i / m.h, k);
+      const gdbl *Ab = gp(At(i, k));
+      gdbl *Vg = gp(Vt);
+      for (int c = 0; c < ncol; ++c)
+        for (int r = tid_x(); r < mrows; r += NTHR)
+          Vg[r + (int64_t)c * nb] = r <= c ? Ab[r + (int64_t)c * lda] : 0.0;
+      __syncthreads();
+      panel_task<RW>(m, L, true, At(tree_partner(m, i, k), k), Vt, nb,
+                     m.T + tree_T_offset(m, i / m.h, k), mrows, ncol);
+    }
     __builtin_amdgcn_s_setprio(0);
     return;
   }
-  auto At = [&](int r, int c) { return m.A + (int64_t)c * nb * m.lda + (int64_t)r * nb; };
-  auto Tt = [&](int r, int c) { return m.T + ((int64_t)c * m.MT + r) * (int64_t)ib * nb; };
-  const int64_t lda = m.lda;
   const int c0 = strip * m.w;
-  const bool onB = type == TK_LARFB_B || type == TK_SSRFB_B;
+  const bool onB = task_on_B(type);
   const bool larfb = type == TK_LARFB || type == TK_LARFB_B;
+  const bool merge = type == TK_TTMQR || type == TK_TTMQR_B;
   const double *aV, *aT;
-  int vrows, kind, kref;
-  if (larfb) {
-    const int mb = tile_rows(m, k);
-    aV = At(k, k);
-    vrows = mb;
+  int64_t ldv = lda;
+  int vrows = tile_rows(m, i), kind = VK_FULL, kref = tile_cols(m, k), top = i;
+  if (larfb) {  // the head's GEQRT reflectors (unit lower part of A_ik)
+    aV = At(i, k);
     kind = VK_UNIT;
-    kref = min(mb, tile_cols(m, k));
-    aT = Tt(k, k);
+    kref = min(vrows, kref);
+    aT = Tt(i, k);
+  } else if (merge) {  // a merge's reflector block
+    aV = m.T + tree_V_offset(m, i / m.h, k);
+    ldv = nb;
+    aT = m.T + tree_T_offset(m, i / m.h, k);
+    top = tree_partner(m, i, k);
   } else {
     aV = At(i, k);
-    vrows = tile_rows(m, i);
-    kind = VK_FULL;
-    kref = tile_cols(m, k);
     aT = Tt(i, k);
+    top = tree_head(m, i, k);
   }
   double *aC1 = nullptr, *aC2;
   int64_t ldc = lda;
@@ -1235,23 +1254,14 @@ __device__ __forceinline__ void run_task(const Task &t, const MatDesc &m, const 
   if (onB) {
     ncols = min(m.w, m.nrhs - c0);
     ldc = m.ldb;
-    double *Bk = m.B + (int64_t)k * nb + (int64_t)c0 * m.ldb;
-    if (larfb) {
-      aC2 = Bk;
-    } else {
-      aC1 = Bk;
-      aC2 = m.B + (int64_t)i * nb + (int64_t)c0 * m.ldb;
-    }
+    aC2 = m.B + (int64_t)i * nb + (int64_t)c0 * m.ldb;
+    if (!larfb) aC1 = m.B + (int64_t)top * nb + (int64_t)c0 * m.ldb;
   } else {
     ncols = min(m.w, tile_cols(m, j) - c0);
-    if (larfb) {
-      aC2 = At(k, j) + (int64_t)c0 * lda;
-    } else {
-      aC1 = At(k, j) + (int64_t)c0 * lda;
-      aC2 = At(i, j) + (int64_t)c0 * lda;
-    }
+    aC2 = At(i, j) + (int64_t)c0 * lda;
+    if (!larfb) aC1 = At(top, j) + (int64_t)c0 * lda;
   }
-  apply_cols<RW>(L, aV, lda, vrows, kind, kref, ib, aT, ib, aC1, ldc, aC2, ldc, ncols);
+  apply_cols<RW>(L, aV, ldv, vrows, kind, kref, ib, aT, ib, aC1, ldc, aC2, ldc, ncols);
 }
 
 // The task's matrix descriptor, field by field from the batch array or the
@@ -1280,6 +1290,8 @@ __device__ __forceinline__ MatDesc load_desc(const MatDesc *__restrict__ mats, i
   m.nrhs = g->nrhs;
   m.SB = g->SB;
   m.gmax = g->gmax;
+  m.h = g->h;
+  m.D = g->D;
   return m;
 }
 
@@ -1503,6 +1515,8 @@ hipError_t tq_launch_ssrfb_bench(double *buf, int nb, int ib, int calls, int gri
   m.ib = ib;
   m.w = strip_width(nb);
   m.gmax = lp.gmax;
+  m.h = 1;
+  m.D = 1;
   const size_t lds = (size_t)lp.doubles * 8;
   hipError_t e = set_lds((const void *)tq_ssrfb_bench, lds);
   if (e != hipSuccess) return e;

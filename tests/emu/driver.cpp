@@ -1,6 +1,7 @@
 // Runs the library's tile-QR kernels under the CPU emulation and compares
-// the results with the C oracle: `emu_qr M N NB IB` (factor + Q^T A) or
-// `emu_qr batch COUNT SEED` (one launch over uneven matrices).
+// the results with the C oracle: `emu_qr M N NB IB [P]` (factor + Q^T A
+// with P row domains) or `emu_qr batch COUNT SEED` (one
+// launch over uneven matrices).
 #include <hip/hip_runtime.h>
 #include <cstdio>
 #include <vector>
@@ -88,6 +89,7 @@ int main(int argc, char **argv) {
   if (std::string(argv[1]) == "batch") return batch_main(atoi(argv[2]), atoi(argv[3]));
   if (std::string(argv[1]) == "decode") { g_decode = true; ++argv; }
   int M = atoi(argv[1]), N = atoi(argv[2]), nb = atoi(argv[3]), ib = atoi(argv[4]);
+  const int p = argc > 5 && !g_decode ? atoi(argv[5]) : 1;
   int64_t lda = M;
   std::mt19937_64 g(M * 7 + N);
   std::uniform_real_distribution<double> U(-1, 1);
@@ -95,10 +97,10 @@ int main(int argc, char **argv) {
   for (auto &x : A) x = U(g);
   A0 = A; Ao = A;
   MatDesc md; memset(&md, 0, sizeof md);
-  md_init(md, M, N, nb, ib, strip_width(nb), M);
+  md_init(md, M, N, nb, ib, strip_width(nb), M, p);
   md.gmax = lds_plan(nb, ib).gmax;
   md.lda = lda;
-  std::vector<double> T((size_t)md.KT * md.MT * ib * nb + 1, std::nan(""));
+  std::vector<double> T((size_t)T_doubles(md) + 1, std::nan(""));
   md.A = A.data(); md.T = T.data();
   if (run({md}, false, 1)) return 1;
   int K = std::min(M, N);
@@ -120,6 +122,6 @@ int main(int argc, char **argv) {
     double d = B[i + (size_t)j * lda] - r; rn += d * d; an += A0[i + (size_t)j * lda] * A0[i + (size_t)j * lda];
   }
   const double rrel = sqrt(num / den), res = sqrt(rn / an);
-  printf("M=%d N=%d nb=%d ib=%d  R_rel=%.3e  resid=%.3e\n", M, N, nb, ib, rrel, res);
+  printf("M=%d N=%d nb=%d ib=%d p=%d (h=%d)  R_rel=%.3e  resid=%.3e\n", M, N, nb, ib, p, md.h, rrel, res);
   return (rrel < 1e-12 && res < 1e-13) ? 0 : 1;
 }

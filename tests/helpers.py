@@ -20,34 +20,41 @@ def to_host(t):
     return np.asfortranarray(t.detach().cpu().numpy())
 
 
-def factor_gpu(A, nb, ib, extra_ld=0, units=None):
+def factor_gpu(A, nb, ib, extra_ld=0, units=None, p=None):
     """Factor a numpy matrix on the GPU, on a grid sized for `units` compute
-    units (None: all of them). Returns (VR host, T device, A dev)."""
+    units (None: all of them); p: row domains of qr_factor_ca (None:
+    qr_factor). Returns (VR host, T device, A dev)."""
     import paper_1102_5328_amd as tq
     import torch
     dA = to_dev(A, extra_ld)
     with grid_units(units):
-        _, T, _, _ = tq.factor(dA, nb, ib)
+        if p is None:
+            _, T, _, _ = tq.factor(dA, nb, ib)
+        else:
+            _, T = tq.factor_ca(dA, nb, ib, p)
         tq.sync()
     torch.cuda.synchronize()
     return to_host(dA), T, dA
 
 
-def apply_qt_gpu(dA, T, nb, ib, B):
+def apply_qt_gpu(dA, T, nb, ib, B, p=None):
     import paper_1102_5328_amd as tq
     dB = to_dev(B)
-    tq.apply_Qt(dA, T, nb, ib, dB)
+    if p is None:
+        tq.apply_Qt(dA, T, nb, ib, dB)
+    else:
+        tq.apply_Qt_ca(dA, T, nb, ib, p, dB)
     tq.sync()
     return to_host(dB)
 
 
-def check_factorization(A, nb, ib, extra_ld=0, cond=None, full_orth=True, units=None):
-    """Factor A on the GPU (grid sized for `units` compute units, None: all)
-    and check it against the oracle and the invariants. Returns a dict of
-    the measured quantities."""
+def check_factorization(A, nb, ib, extra_ld=0, cond=None, full_orth=True, units=None, p=None):
+    """Factor A on the GPU (grid sized for `units` compute units, None: all;
+    p row domains, None: the flat qr_factor) and check it against the oracle
+    and the invariants. Returns a dict of the measured quantities."""
     M, N = A.shape
     K = min(M, N)
-    VR, T, dA = factor_gpu(A, nb, ib, extra_ld, units)
+    VR, T, dA = factor_gpu(A, nb, ib, extra_ld, units, p)
     VRo, tauo = oracle.geqr2(A)
     R_g, R_o = oracle.upper(VR), oracle.upper(VRo)
     out = {}
@@ -58,11 +65,11 @@ def check_factorization(A, nb, ib, extra_ld=0, cond=None, full_orth=True, units=
     bound = oracle.invariant_bound(M, N)
     nA = np.linalg.norm(A)
     # ||A - QR|| / ||A|| = ||Q^T A - [R; 0]|| / ||A|| for orthogonal Q.
-    E = apply_qt_gpu(dA, T, nb, ib, A)
+    E = apply_qt_gpu(dA, T, nb, ib, A, p)
     E[:K] -= R_g
     out["residual"] = np.linalg.norm(E) / nA if nA > 0 else 0.0
     if full_orth:
-        Qt = apply_qt_gpu(dA, T, nb, ib, np.eye(M))
+        Qt = apply_qt_gpu(dA, T, nb, ib, np.eye(M), p)
         out["orth"] = np.linalg.norm(np.eye(M) - Qt @ Qt.T)
     out["bound"] = bound
     return out

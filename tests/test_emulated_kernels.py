@@ -4,7 +4,7 @@ device, MFMA with the measured gfx950 lane layout) with AddressSanitizer:
 the index arithmetic of every task kind stays in bounds, and the results
 match the oracle. Covers every row-wave class (NB <= 128: one wave per
 128-row slab of a column group; NB <= 256: two; NB <= 512: four), ragged
-tiles, inner blocks that do not divide NB, inner blocks wider than a
+tiles, inner blocks that do not divide NB, the communication-avoiding tree, inner blocks wider than a
 register panel (the T assembly across panels), the batched union DAG and
 the MLP kernels. Runs on the CPU; slow (a few minutes in all)."""
 import os
@@ -45,6 +45,19 @@ def _run(args, timeout=600):
 ])
 def test_tile_qr_emulated(emu, M, N, nb, ib):
     out = _run([emu[0], str(M), str(N), str(nb), str(ib)])
+    assert "R_rel" in out
+
+
+@pytest.mark.parametrize("M,N,nb,ib,p", [
+    (300, 100, 64, 16, 2),   # two domains: chains, one merge per step
+    (520, 200, 64, 16, 9),   # one tile row per domain, ragged: the tree alone
+    (450, 130, 64, 12, 3),   # IB does not divide NB
+    (330, 330, 64, 16, 2),   # square, trailing merges on every step
+    (420, 100, 136, 16, 3),  # two row waves, ragged last domain head
+])
+def test_ca_tree_emulated(emu, M, N, nb, ib, p):
+    # communication-avoiding variant: p row domains merged over a binary tree
+    out = _run([emu[0], str(M), str(N), str(nb), str(ib), str(p)])
     assert "R_rel" in out
 
 

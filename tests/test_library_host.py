@@ -76,9 +76,82 @@ def test_factor_noalloc_argument_errors(lib):
     assert f(p, 8, 4, 8, 64, 65, p, None) == -6
     assert f(p, 8, 4, 8, 64, 16, None, None) == -7
     # 65536 x 16384 with NB = 16: 4096 x 1024 tiles, one strip each, plus
-    # 1024 panel counters: more than the 4 Mi ints of the scratch
+    # 1024 x 4096 panel counters: more than the 4 Mi ints of the scratch
     assert f(p, 65536, 16384, 65536, 16, 16, p, None) == 5  # TILEQR_ERR_TOO_LARGE
     assert f(p, 0, 16, 1, 64, 16, p, None) == 0  # empty: nothing to do
+
+
+def test_ca_argument_errors(lib):
+    # qr_factor_ca / qr_apply_Qt_ca: p in position 7; all checks return
+    # before any device call
+    f = lib.qr_factor_ca
+    p = ctypes.c_void_p(16)
+    assert f(p, -1, 4, 4, 64, 16, 2, p, None) == -2
+    assert f(None, 4, 4, 4, 64, 16, 2, p, None) == -1
+    assert f(p, 8, 4, 7, 64, 16, 2, p, None) == -4
+    assert f(p, 8, 4, 8, 8, 4, 2, p, None) == -5
+    assert f(p, 8, 4, 8, 64, 65, 2, p, None) == -6
+    assert f(p, 8, 4, 8, 64, 16, -1, p, None) == -7
+    assert f(p, 8, 4, 8, 64, 16, 2, None, None) == -8
+    g = lib.qr_apply_Qt_ca
+    assert g(p, 8, 4, 8, 64, 16, -3, p, p, 2, 8, None) == -7
+    assert g(p, 8, 4, 8, 64, 16, 2, None, p, 2, 8, None) == -8
+    assert g(p, 8, 4, 8, 64, 16, 2, p, None, 2, 8, None) == -9
+    assert g(p, 8, 4, 8, 64, 16, 2, p, p, -2, 8, None) == -10
+    assert g(p, 8, 4, 8, 64, 16, 2, p, p, 2, 4, None) == -11
+    assert lib.qr_T_size_ca(8, 4, 64, 16, -1) == -5
+
+
+def test_ca_T_size(lib):
+    """The T buffer of p domains: the per-tile T factors, then one NB x NB
+    reflector block and one IB x NB T factor per (step, domain)."""
+    M, N, nb, ib = 1000, 300, 64, 16
+    MT, NT = 16, 5
+    KT = min(MT, NT)
+    base = KT * MT * ib * nb
+    assert tq.T_size(M, N, nb, ib) == base
+    assert tq.T_size(M, N, nb, ib, 1) == base
+    for p, D in ((2, 2), (5, 4), (16, 16), (100, 16)):  # h = ceil(MT/p), D = ceil(MT/h)
+        assert tq.T_size(M, N, nb, ib, p) == base + KT * D * (nb * nb + ib * nb)
+
+
+@pytest.mark.parametrize("M,N,nb,ib,p,workers,apply,nrhs", [
+    (1000, 200, 64, 16, 2, 64, False, 0),
+    (1000, 200, 64, 16, 5, 7, False, 0),     # ragged last domain
+    (1000, 200, 64, 16, 16, 256, False, 0),  # one row per domain
+    (700, 150, 128, 32, 3, 32, True, 40),
+    (600, 600, 64, 16, 4, 64, False, 0),
+    (300, 700, 64, 32, 3, 16, True, 9),
+    (4096, 128, 64, 16, 64, 16, False, 0),
+])
+def test_ca_plan_is_a_valid_schedule(lib, M, N, nb, ib, p, workers, apply, nrhs):
+    """Tree DAGs: the ticket order replays with every wait satisfied, and the
+    randomized parallel replay shows no hazard on tiles, the merges'
+    reflector blocks or B."""
+    for seed in (0, 1):
+        nt, seq, stress = tq.plan_check(M, N, nb, ib, nrhs=nrhs, apply=apply, workers=workers,
+                                        seed=seed, p=p)
+        assert nt > 0 and seq == 0 and stress == 0
+
+
+def test_ca_plan_task_multiset(lib):
+    """Per step k of a 16 x 2 tile grid in domains of h = 4 rows: a GEQRT
+    per domain head, a TSQRT per other row, and one merge per active domain
+    but the first (the tree of E domains has E - 1 merges), each merge
+    updating the trailing columns once."""
+    tasks = tq.plan_tasks(1024, 128, 64, 16, p=4, workers=8)
+    h, MT = 4, 16
+    for k in range(2):
+        rows = range(k, MT)
+        heads = {i for i in rows if i == k or i % h == 0}
+        ge = {int(t[1]) for t in tasks if t[0] == 0 and t[3] == k}
+        ts = {int(t[1]) for t in tasks if t[0] == 1 and t[3] == k}
+        tt = sorted(int(t[1]) for t in tasks if t[0] == 6 and t[3] == k)
+        assert ge == heads
+        assert ts == set(rows) - heads
+        assert tt == sorted(i for i in heads if i != k)
+        ttm = [(int(t[1]), int(t[2])) for t in tasks if t[0] == 7 and t[3] == k]
+        assert sorted(i for i, j in ttm) == (tt if k == 0 else [])
 
 
 def test_apply_argument_errors(lib):
@@ -245,6 +318,36 @@ def test_tune_interpolation_examples(lib, tmp_path, monkeypatch):
         tq.tune_load(_table(tmp_path, []))
     # An empty table: the default, source 0.
     assert tq.tune(5000, 5000, 1) == (128, 32, 0)
+
+
+def test_tune_budget_sections_and_domains(lib, tmp_path, monkeypatch):
+    """Entries under "budget C" serve callers limited to C compute units; a
+    caller without a setting (the whole device) takes the "all" section when
+    there is one, else the nearest budget. The optional eighth field of an
+    entry is the tree's domain count, which p = 0 resolves to."""
+    monkeypatch.delenv("TILEQR_NB", raising=False)
+    monkeypatch.delenv("TILEQR_IB", raising=False)
+    p = tmp_path / "budget.txt"
+    p.write_text("default 128 32\n"
+                 "entry 4000 4000 1 128 16 9.0 192\n"
+                 "entry 65536 256 1 64 16 1.0 0 128\n"
+                 "budget 64\n"
+                 "entry 4000 4000 1 96 32 5.0\n")
+    tq.tune_load(str(p))
+    try:
+        assert tq.tune(4000, 4000, 1) == (128, 16, 1)
+        assert tq.tune_units(4000, 4000, 1) == 192
+        MT, KT, D = 1024, 4, 128
+        assert tq.T_size(65536, 256, 64, 16, 0) == KT * MT * 16 * 64 + KT * D * (64 * 64 + 16 * 64)
+        p.write_text("budget 64\nentry 4000 4000 1 96 32 5.0\n")
+        tq.tune_load(str(p))
+        assert tq.tune(4000, 4000, 1) == (96, 32, 1)
+        p.write_text("budget -3\nentry 4000 4000 1 96 32 5.0\n")
+        assert lib.qr_tune_load(str(p).encode()) == 7
+        p.write_text("entry 4000 4000 1 96 32 5.0 0 0\n")  # p < 1
+        assert lib.qr_tune_load(str(p).encode()) == 7
+    finally:
+        tq.tune_load(_table(tmp_path, []))
 
 
 def test_tune_load_rejects_malformed(lib, tmp_path):
