@@ -237,6 +237,12 @@ int qr_tune(int64_t M, int64_t N, int64_t batch, int *NB, int *IB, int *source);
  * -4 cus null. */
 int qr_tune_units(int64_t M, int64_t N, int64_t batch, int *cus);
 
+/* Host only. The row-domain count p of qr_factor_ca (p = 0 there) for an
+ * M x N factorization: the decision table's nearest entry's (1 without a
+ * table or when the entry has none). Errors: -1 M, -2 N, -3 batch, -4 p
+ * null. */
+int qr_tune_domains(int64_t M, int64_t N, int64_t batch, int *p);
+
 /* Loads a decision table (host path; text: lines "entry M N batch NB IB
  * gflops [units [p]]", where units is the compute-unit count the grid is
  * sized for, 0 or absent for all, and p the row domains of qr_factor_ca

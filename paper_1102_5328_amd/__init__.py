@@ -88,6 +88,15 @@ def tune_units(M, N, batch=1):
     return cus.value
 
 
+def tune_domains(M, N, batch=1):
+    """Row domains of qr_factor_ca for an M x N factorization (table; 1 when
+    absent)."""
+    _ensure_table()
+    p = ctypes.c_int()
+    check(_lib.lib().qr_tune_domains(M, N, batch, ctypes.byref(p)), "qr_tune_domains")
+    return p.value
+
+
 def tune_load(path):
     global _table_loaded
     check(_lib.lib().qr_tune_load(path.encode()), "qr_tune_load")

@@ -45,6 +45,7 @@ SIGNATURES = {
     "qr_tune": (c_int, [c_i64, c_i64, c_i64, c_intp, c_intp, c_intp]),
     "qr_tune_load": (c_int, [ctypes.c_char_p]),
     "qr_tune_units": (c_int, [c_i64, c_i64, c_i64, c_intp]),
+    "qr_tune_domains": (c_int, [c_i64, c_i64, c_i64, c_intp]),
     "qr_tune_set_model": (c_int, [c_fltp, c_int, c_fltp, c_fltp, c_flt, c_flt, c_intp, c_int]),
     "qr_mlp_forward": (c_int, [c_vp, c_int, c_vp, c_i64, c_vp, c_vp]),
     "qr_mlp_grad": (c_int, [c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp]),

@@ -390,7 +390,7 @@ int units_for(int64_t M, int64_t N, int64_t batch) {
 }
 
 // Row domains of the reduction tree for one matrix: the nearest entry's
-// (tuned with its tile order; 1 without a table).
+// (tuned with its tile order; 1 without a table). Called with g_mu held.
 int domains_for(int64_t M, int64_t N, int nb) {
   (void)nb;
   const TableEntry *e = nearest_entry(M, N, 1);
@@ -423,7 +423,10 @@ int64_t qr_T_size_ca(int64_t M, int64_t N, int NB, int IB, int p) {
   if (IB < 1 || IB > NB) return -4;
   if (p < 0) return -5;
   if (M > INT32_MAX || N > INT32_MAX) return -1;
-  if (p == 0) p = domains_for(M, N, NB);
+  if (p == 0) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    p = domains_for(M, N, NB);
+  }
   MatDesc md;
   std::memset(&md, 0, sizeof(md));
   md_init(md, M, N, NB, IB, strip_width(NB), 0, p);
@@ -448,8 +451,8 @@ int qr_factor_ca(double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, i
   if (IB < 1 || IB > NB) return -6;
   if (!T && M * N > 0) return -8;
   if (!nb_enabled(NB)) return TILEQR_ERR_DISABLED;
-  if (p == 0) p = domains_for(M, N, NB);
   std::lock_guard<std::mutex> lk(g_mu);
+  if (p == 0) p = domains_for(M, N, NB);
   DevState *ds;
   if ((rc = dev_state(&ds))) return rc;
   return factor_one(A, M, N, lda, NB, IB, p, T, (hipStream_t)stream, *ds);
@@ -543,8 +546,8 @@ int qr_apply_Qt_ca(const double *A, int64_t M, int64_t N, int64_t lda, int NB, i
   if (M > INT32_MAX || N > INT32_MAX || nrhs > INT32_MAX) return TILEQR_ERR_TOO_LARGE;
   if (!nb_enabled(NB)) return TILEQR_ERR_DISABLED;
   if (M == 0 || N == 0 || nrhs == 0) return 0;
-  if (p == 0) p = domains_for(M, N, NB);
   std::lock_guard<std::mutex> lk(g_mu);
+  if (p == 0) p = domains_for(M, N, NB);
   DevState *ds;
   if ((rc = dev_state(&ds))) return rc;
   MatDesc md;
@@ -1010,6 +1013,17 @@ int qr_tune(int64_t M, int64_t N, int64_t batch, int *NB, int *IB, int *source) 
   *NB = nb;
   *IB = std::min(ib, nb);
   if (source) *source = src;
+  return 0;
+}
+
+int qr_tune_domains(int64_t M, int64_t N, int64_t batch, int *p) {
+  if (M < 0) return -1;
+  if (N < 0) return -2;
+  if (batch < 1) return -3;
+  if (!p) return -4;
+  std::lock_guard<std::mutex> lk(g_mu);
+  const TableEntry *e = nearest_entry(M, N, batch);
+  *p = e && e->p > 0 ? e->p : 1;
   return 0;
 }
 

@@ -243,41 +243,68 @@ def tune(out_dir, db):
     return rep
 
 
-def ship_table(tune_dir, out_path, heuristic="2r", batch_count=2000, src_name=None):
-    """The decision table the library ships: the Step-2 decisions for single
-    matrices (`src_name` in tune_dir, by default heuristic's PSPAYG table;
-    entries may carry a unit count) plus the per-size-class decisions of the
-    batched tuning (entries with the batch count)."""
-    src = os.path.join(tune_dir, src_name or "decision_table_h%s_pspayg.txt" % heuristic)
-    entries = []
-    default = (128, 16)
-    with open(src) as f:
+def _read_entries(path):
+    """Entries of a decision table file: (M, N, batch, NB, IB, gflops, units, p)."""
+    out = []
+    with open(path) as f:
         for line in f:
             w = line.split()
             if w and w[0] == "entry":
-                entries.append(tuple(int(x) for x in w[1:6]) + (float(w[6]),) +
-                               ((int(w[7]),) if len(w) > 7 else (0,)))
+                out.append(tuple(int(x) for x in w[1:6]) + (float(w[6]),) +
+                           ((int(w[7]),) if len(w) > 7 else (0,)) +
+                           ((int(w[8]),) if len(w) > 8 else (1,)))
+    return out
+
+
+def _write_entry(f, e):
+    M, N, b, nb, ib, g, u, p = e
+    if p > 1:
+        f.write("entry %d %d %d %d %d %.3f %d %d\n" % (M, N, b, nb, ib, g, u, p))
+    elif u:
+        f.write("entry %d %d %d %d %d %.3f %d\n" % (M, N, b, nb, ib, g, u))
+    else:
+        f.write("entry %d %d %d %d %d %.3f\n" % (M, N, b, nb, ib, g))
+
+
+def ship_table(tune_dir, out_path, heuristic="2r", batch_count=2000, src_name=None):
+    """The decision table the library ships: the Step-2 decisions for single
+    matrices (`src_name` in tune_dir, by default heuristic's PSPAYG table;
+    entries may carry a unit count and a row-domain count) plus the
+    per-size-class decisions of the batched tuning (entries with the batch
+    count), then one section per compute-unit budget tuned by tune-budgets
+    (decision_table_budget_C.txt)."""
+    src = os.path.join(tune_dir, src_name or "decision_table_h%s_pspayg.txt" % heuristic)
+    entries = _read_entries(src)
+    default = (128, 16)
     bt = os.path.join(tune_dir, "batched_tune.json")
     if os.path.exists(bt):
         with open(bt) as f:
             for k, (nb, ib, g) in json.load(f).items():
                 m, n = (int(x) for x in k.split("x"))
-                entries.append((m, n, batch_count, nb, ib, g, 0))
+                entries.append((m, n, batch_count, nb, ib, g, 0, 1))
     big = max((e for e in entries if e[2] == 1), key=lambda e: e[0] * e[1], default=None)
     if big is not None:
         default = (big[3], big[4])
+    budgets = []
+    for name in sorted(os.listdir(tune_dir)):
+        if name.startswith("decision_table_budget_") and name.endswith(".txt"):
+            c = int(name[len("decision_table_budget_"):-4])
+            budgets.append((c, _read_entries(os.path.join(tune_dir, name))))
+    budgets.sort()
     with open(out_path, "w") as f:
-        f.write("# tileqr decision table: entry M N batch NB IB gflops [units; absent: all]\n")
-        f.write("# single matrices: Step 2 over the pairs of heuristic %s (%s);\n"
-                % (heuristic, os.path.basename(src)))
+        f.write("# tileqr decision table: entry M N batch NB IB gflops [units [p]]\n")
+        f.write("# single matrices: Step 2 over the pairs of heuristic %s (%s), each pair at\n"
+                "# its best row-domain count p;\n" % (heuristic, os.path.basename(src)))
         f.write("# batch %d: per size class (M, N rounded up to powers of two; the entry holds\n"
                 "# the class's geometric-mean shape)\n" % batch_count)
         f.write("default %d %d\n" % default)
         for e in sorted(entries, key=lambda e: (e[2], e[0], e[1])):
-            if e[6]:
-                f.write("entry %d %d %d %d %d %.3f %d\n" % e)
-            else:
-                f.write("entry %d %d %d %d %d %.3f\n" % e[:6])
+            _write_entry(f, e)
+        for c, ents in budgets:
+            f.write("# callers limited to %d compute units (qr_set_compute_units)\n" % c)
+            f.write("budget %d\n" % c)
+            for e in sorted(ents, key=lambda e: (e[2], e[0], e[1])):
+                _write_entry(f, e)
     return entries
 
 
@@ -425,6 +452,47 @@ def tune_units(out_dir, db, units_list=(64, 128, 0)):
            "test": rows, "avg_pct_of_es_pairs": round(float(np.mean([r["pct_of_es_pairs"]
                                                                     for r in rows])), 2)}
     with open(os.path.join(out_dir, "tune_units_report.json"), "w") as f:
+        json.dump(rep, f, indent=1)
+    return rep
+
+
+BUDGET_GRID = [(1024, 1024), (2048, 2048), (4096, 4096), (8192, 8192),
+               (16384, 256), (65536, 256), (4096, 1024), (16384, 1024)]
+
+
+def tune_budgets(out_dir, db, budgets=(32, 64, 128)):
+    """The (size, compute units) decision of Section 6.1 (the paper
+    interpolates over the core count): for each budget C, Step 2 (PSPAYG) of
+    the shipped heuristic's pre-selected pairs, each at its best row-domain
+    count, on a stream restricted to C compute units with the grid sized for
+    them; the decisions go to decision_table_budget_C.txt, a section that
+    qr_tune consults for callers limited to C units."""
+    import torch
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    ps = shipped_preselection()
+    meas = R.Measurer(db, reps=4)
+    rep = {"preselected": [list(p) for p in ps], "grid": ["%dx%d" % s for s in BUDGET_GRID]}
+    for c in budgets:
+        hip, st = _cu_masked_stream(c, ncu)
+        meas.masked = (c, torch.cuda.ExternalStream(st.value))
+        try:
+            m = lambda M, N, nb, ib: meas.measure_best_p(M, N, nb, ib, units=c)[:2]
+            table, t = S2.step2(BUDGET_GRID, ps, m, payg=True)
+            dec = {}
+            for s_, d in S2.decisions(table).items():
+                p = meas.measure_best_p(s_[0], s_[1], d[0], d[1], units=c)[2]
+                dec[s_] = (d[0], d[1], d[2], c, p)
+        finally:
+            meas.masked = None
+            torch.cuda.synchronize()
+            hip.hipStreamDestroy(st)
+        meas.save()
+        S2.write_table(os.path.join(out_dir, "decision_table_budget_%d.txt" % c), dec,
+                       comment="heuristic 2r pairs, PSPAYG, %d compute units (masked stream)" % c)
+        rep[str(c)] = {"step2_seconds": t,
+                       "decisions": {"%dx%d" % k: list(v) for k, v in dec.items()}}
+        log("budget %d: step2 %.1f s, %s" % (c, t, {"%dx%d" % k: v[:2] + v[4:] for k, v in dec.items()}))
+    with open(os.path.join(out_dir, "tune_budgets_report.json"), "w") as f:
         json.dump(rep, f, indent=1)
     return rep
 
@@ -679,7 +747,7 @@ def _lib_set_model(params, nmodels, fmean, fstd, ymean, ystd, cand):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("what", choices=["batched", "batched-tune", "sweep", "tune", "step1-cold",
-                                     "cu-scaling", "tune-units", "ship",
+                                     "cu-scaling", "tune-units", "tune-budgets", "ship",
                                      "collect-train",
                                      "collect-heldout", "mlp"])
     ap.add_argument("--out", required=True)
@@ -710,6 +778,8 @@ def main(argv=None):
         cu_scaling(a.out)
     elif a.what == "tune-units":
         tune_units(a.out, db, tuple(int(x) for x in a.units.split(",")))
+    elif a.what == "tune-budgets":
+        tune_budgets(a.out, db)
     elif a.what in ("collect-train", "collect-heldout"):
         done = collect(db, a.what.split("-")[1], a.budget)
         log("collect %s: %s" % (a.what, "complete" if done else "budget reached"))

@@ -30,6 +30,21 @@ def config2_pairs(nbs=(64, 96, 128, 192, 256, 384, 512), ib_min=16, max_nb=ENABL
     return out
 
 
+def domain_candidates(M, N, nb):
+    """Row-domain counts p of the communication-avoiding tree tried for an
+    M x N shape with tile order nb: the flat tree (p = 1) and, for tall
+    shapes (M >= 4N, whose panels are long chains), domains of 8, 4, 2 and 1
+    tile rows."""
+    MT = -(-M // nb)
+    out = [1]
+    if M >= 4 * N:
+        for h in (8, 4, 2, 1):
+            p = -(-MT // h)
+            if p > 1 and p not in out:
+                out.append(p)
+    return out
+
+
 class Measurer:
     """Times tile QR factorizations on cuda:0 (median of `reps` runs after one
     warm-up, each on a fresh copy of the same seeded input), with a JSON
@@ -47,6 +62,9 @@ class Measurer:
                 self.db = json.load(f)
         self._shape = None
         self._A0 = None
+        # (units, torch stream): runs with that unit count go to a stream
+        # restricted to those compute units (a caller's masked stream)
+        self.masked = None
 
     def save(self):
         if self.db_path:
@@ -56,9 +74,9 @@ class Measurer:
             os.replace(tmp, self.db_path)
 
     @staticmethod
-    def key(kind, M, N, nb, ib, batch=1, units=0):
+    def key(kind, M, N, nb, ib, batch=1, units=0, p=1):
         k = "%s:%d:%d:%d:%d:%d" % (kind, M, N, nb, ib, batch)
-        return k + (":u%d" % units if units else "")
+        return k + (":u%d" % units if units else "") + (":p%d" % p if p > 1 else "")
 
     def _input(self, kind, M, N):
         import torch
@@ -75,10 +93,22 @@ class Measurer:
             self._shape = (kind, M, N)
         return self._A0
 
-    def measure(self, M, N, nb, ib, kind="normal", reps=None, units=0):
+    def measure_best_p(self, M, N, nb, ib, kind="normal", units=0):
+        """The pair at its best row-domain count: (median GFLOP/s, seconds
+        spent over every count tried, p)."""
+        best, sec = None, 0.0
+        for p in domain_candidates(M, N, nb):
+            g, t = self.measure(M, N, nb, ib, kind=kind, units=units, p=p)
+            sec += t
+            if best is None or g > best[0]:
+                best = (g, p)
+        return best[0], sec, best[1]
+
+    def measure(self, M, N, nb, ib, kind="normal", reps=None, units=0, p=1):
         """(median GFLOP/s, seconds spent) for one configuration; units > 0
-        sizes the persistent grid for that many compute units, 0 for all."""
-        k = self.key(kind, M, N, nb, ib, units=units)
+        sizes the persistent grid for that many compute units, 0 for all; p
+        row domains of the communication-avoiding tree (1: flat)."""
+        k = self.key(kind, M, N, nb, ib, units=units, p=p)
         if k in self.db:
             r = self.db[k]
             return r["gflops"], r["seconds"]
@@ -89,31 +119,34 @@ class Measurer:
         reps = reps or self.reps
         A0 = self._input(kind, M, N)
         A = tq.colmajor(M, N)
-        T = torch.empty(max(1, tq.T_size(M, N, nb, ib)), dtype=torch.float64, device="cuda")
+        T = torch.empty(max(1, tq.T_size(M, N, nb, ib, p)), dtype=torch.float64, device="cuda")
         fl = tq.flops(M, N)
-        import torch as _t
-        tq.set_compute_units(units if units else _t.cuda.get_device_properties(0).multi_processor_count)
+        tq.set_compute_units(units if units else torch.cuda.get_device_properties(0).multi_processor_count)
+        st = self.masked[1] if (self.masked and units == self.masked[0]) else torch.cuda.current_stream()
+        torch.cuda.synchronize()
         t_start = time.perf_counter()
         A.copy_(A0)
-        tq.factor(A, nb, ib, T)
-        tq.sync()
+        torch.cuda.synchronize()
+        tq.factor_ca(A, nb, ib, p, T, stream=st)
+        tq.sync(st)
         g = []
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         for _ in range(reps):
             A.copy_(A0)
-            e0.record()
-            tq.factor(A, nb, ib, T)
-            e1.record()
-            tq.sync()
+            torch.cuda.synchronize()
+            e0.record(st)
+            tq.factor_ca(A, nb, ib, p, T, stream=st)
+            e1.record(st)
+            tq.sync(st)
             g.append(fl / (e0.elapsed_time(e1) * 1e-3) / 1e9)
         sec = time.perf_counter() - t_start
         tq.set_compute_units(0)
         med = S2.median(g)
         self.db[k] = {"gflops": med, "max": max(g), "runs": g, "seconds": sec, "M": M, "N": N,
-                      "nb": nb, "ib": ib, "batch": 1, "kind": kind, "units": units}
+                      "nb": nb, "ib": ib, "batch": 1, "kind": kind, "units": units, "p": p}
         if self.verbose:
-            print("measured %s %dx%d nb=%d ib=%d: %.1f GFLOP/s (%.2f s)" % (kind, M, N, nb, ib, med, sec),
-                  flush=True)
+            print("measured %s %dx%d nb=%d ib=%d units=%d p=%d: %.1f GFLOP/s (%.2f s)"
+                  % (kind, M, N, nb, ib, units, p, med, sec), flush=True)
         del A, T
         return med, sec
 
@@ -160,22 +193,30 @@ def tune_search(measurer, out_dir, pairs=None, heuristics_=(0, 1, 2, "2r"), k=8,
     pairs = pairs or config2_pairs()
     s1, t_step1 = step1 if step1 is not None else step1_gpu(pairs)
     log("step1 %.1f s: %s" % (t_step1, {"%dx%d" % p: round(v, 1) for p, v in s1.items()}))
-    meas = lambda M, N, nb, ib: measurer.measure(M, N, nb, ib)
+    # each (NB, IB) is timed at its best row-domain count (the flat tree for
+    # all but tall shapes); the tables record that count
+    meas = lambda M, N, nb, ib: measurer.measure_best_p(M, N, nb, ib)[:2]
+    best_p = lambda M, N, nb, ib, kind="normal": measurer.measure_best_p(M, N, nb, ib, kind=kind)[2]
+
+    def with_p(dec):
+        return {s: (d[0], d[1], d[2], 0, best_p(s[0], s[1], d[0], d[1])) for s, d in dec.items()}
+
     report = {"pairs": pairs, "step1_seconds": t_step1,
               "step1_gflops": {"%d,%d" % p: v for p, v in s1.items()}, "heuristics": {}}
-    # Exhaustive search on the test shapes (the reference).
+    # Exhaustive search on the test shapes (the reference): every pair at
+    # every row-domain count.
     es = {}
     for kind, M, N in TEST_SHAPES:
-        res = {p: measurer.measure(M, N, p[0], p[1], kind=kind) for p in pairs}
+        res = {p: measurer.measure_best_p(M, N, p[0], p[1], kind=kind) for p in pairs}
         best = max(res, key=lambda p: res[p][0])
-        es[(kind, M, N)] = (best, res[best][0], {p: v[0] for p, v in res.items()})
-        log("ES %s %dx%d: best %s %.1f GFLOP/s" % (kind, M, N, best, res[best][0]))
+        es[(kind, M, N)] = (best, res[best][0], {p: v[0] for p, v in res.items()}, res[best][2])
+        log("ES %s %dx%d: best %s p=%d %.1f GFLOP/s" % (kind, M, N, best, res[best][2], res[best][0]))
         measurer.save()
     # Exhaustive search over the size grid: its decisions and its tuning time
     # (the sum of the original runs' durations), the Table 1 analog.
     es_table, t_es = S2.step2(STEP2_GRID, pairs, meas, payg=False)
     measurer.save()
-    S2.write_table(os.path.join(out_dir, "decision_table_es.txt"), S2.decisions(es_table),
+    S2.write_table(os.path.join(out_dir, "decision_table_es.txt"), with_p(S2.decisions(es_table)),
                    comment="exhaustive search")
     report["tuning_seconds"] = {"ES": t_es}
     for h in heuristics_:
@@ -184,7 +225,7 @@ def tune_search(measurer, out_dir, pairs=None, heuristics_=(0, 1, 2, "2r"), k=8,
         for payg in (False, True):
             table, t2 = S2.step2(STEP2_GRID, ps, meas, payg=payg)
             measurer.save()
-            dec = S2.decisions(table)
+            dec = with_p(S2.decisions(table))
             name = "PSPAYG" if payg else "PS"
             path = os.path.join(out_dir, "decision_table_h%s_%s.txt" % (h, name.lower()))
             S2.write_table(path, dec, comment="heuristic %s, %s" % (h, name))
@@ -192,23 +233,23 @@ def tune_search(measurer, out_dir, pairs=None, heuristics_=(0, 1, 2, "2r"), k=8,
             chosen, got, ref = [], [], []
             for kind, M, N in TEST_SHAPES:
                 nb, ib, _ = tq.tune(M, N, 1)
-                g = es[(kind, M, N)][2].get((nb, ib))
-                if g is None:
-                    g = measurer.measure(M, N, nb, ib, kind=kind)[0]
-                chosen.append([kind, M, N, nb, ib, g])
+                p = tq.tune_domains(M, N, 1)
+                g = measurer.measure(M, N, nb, ib, kind=kind, p=p)[0]
+                chosen.append([kind, M, N, nb, ib, g, p])
                 got.append(g)
                 ref.append(es[(kind, M, N)][1])
             avg, opt, pct = S2.summary(got, ref)
             report["tuning_seconds"]["H%s_%s" % (h, name)] = t_step1 + t2
             entry[name] = {"step2_seconds": t2, "avg_pct_of_ES": avg, "optimum": opt,
                            "n": len(got), "pct": pct, "chosen": chosen,
-                           "table": {"%dx%d" % s: [d[0], d[1], d[2]] for s, d in dec.items()}}
+                           "table": {"%dx%d" % s: [d[0], d[1], d[2], d[4]] for s, d in dec.items()}}
             log("H%s %s: step2 %.1f s, avg %.2f%% of ES, optimum %d/%d" % (h, name, t2, avg, opt, len(got)))
         avg, opt, _ = S2.summary([c[5] for c in entry["PSPAYG"]["chosen"]],
                                  [c[5] for c in entry["PS"]["chosen"]])
         entry["PSPAYG_over_PS"] = {"avg": avg, "optimum": opt}
         report["heuristics"][str(h)] = entry
-    report["ES"] = {"%s:%dx%d" % s: {"best": list(v[0]), "gflops": v[1]} for s, v in es.items()}
+    report["ES"] = {"%s:%dx%d" % s: {"best": list(v[0]), "p": v[3], "gflops": v[1]}
+                    for s, v in es.items()}
     with open(os.path.join(out_dir, "tuning_report.json"), "w") as f:
         json.dump(report, f, indent=1)
     return report

@@ -78,7 +78,7 @@ def decisions(table):
 def write_table(path, dec, batch=1, default=(128, 32), comment=None):
     """Decision table in the text format read by qr_tune_load."""
     with open(path, "w") as f:
-        f.write("# tileqr decision table: entry M N batch NB IB gflops\n")
+        f.write("# tileqr decision table: entry M N batch NB IB gflops [units [p]]\n")
         if comment:
             for line in comment.splitlines():
                 f.write("# %s\n" % line)
@@ -86,7 +86,10 @@ def write_table(path, dec, batch=1, default=(128, 32), comment=None):
         for (M, N), d in sorted(dec.items()):
             nb, ib, g = d[:3]
             units = d[3] if len(d) > 3 else 0
-            if units:
+            p = d[4] if len(d) > 4 else 1
+            if p > 1:
+                f.write("entry %d %d %d %d %d %.3f %d %d\n" % (M, N, batch, nb, ib, g, units, p))
+            elif units:
                 f.write("entry %d %d %d %d %d %.3f %d\n" % (M, N, batch, nb, ib, g, units))
             else:
                 f.write("entry %d %d %d %d %d %.3f\n" % (M, N, batch, nb, ib, g))

@@ -74,3 +74,22 @@ def test_ship_table_carries_units(tmp_path):
     assert "entry 4096 4096 1 64 16 2300.000 64" in lines
     assert "entry 16384 16384 1 128 16 9200.000" in lines
     assert lines[0] == "default 128 16"
+
+
+def test_ship_table_domains_and_budgets(tmp_path):
+    """Row-domain counts ride along as the eighth field; each tune-budgets
+    output becomes a "budget C" section after the whole-device entries."""
+    d = tmp_path / "run"
+    d.mkdir()
+    (d / "decision_table_h2r_pspayg.txt").write_text(
+        "default 128 16\nentry 65536 256 1 128 16 1355.0 0 256\nentry 16384 16384 1 128 16 24000.0\n")
+    (d / "decision_table_budget_64.txt").write_text("default 128 16\nentry 4096 4096 1 96 32 1500.0\n")
+    (d / "decision_table_budget_128.txt").write_text("default 128 16\nentry 4096 4096 1 128 16 2500.0\n")
+    out = tmp_path / "table.txt"
+    E.ship_table(str(d), str(out))
+    lines = [l for l in out.read_text().splitlines() if not l.startswith("#")]
+    assert "entry 65536 256 1 128 16 1355.000 0 256" in lines
+    i64, i128 = lines.index("budget 64"), lines.index("budget 128")
+    assert lines[i64 + 1] == "entry 4096 4096 1 96 32 1500.000"
+    assert lines[i128 + 1] == "entry 4096 4096 1 128 16 2500.000"
+    assert i64 < i128 and lines.index("entry 16384 16384 1 128 16 24000.000") < i64

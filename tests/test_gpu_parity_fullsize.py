@@ -14,7 +14,8 @@ entry by entry:
     both <= 20 K eps.
 The GPU runs with the tiling and grid the benchmark uses (the shipped
 decision table's (NB, IB) and unit count); the square 4096 and 16384 cases
-run again on the full grid (every compute unit, two workgroups each)."""
+run again on the full grid (every compute unit, two workgroups each), and
+the tall shapes again with the communication-avoiding tree (qr_factor_ca)."""
 import os
 
 import numpy as np
@@ -44,30 +45,36 @@ def _oracle(M, N, seed):
     return _cache[key]
 
 
-def _gpu_check(M, N, seed, units):
+def _gpu_check(M, N, seed, units, tree=None):
+    """tree = (NB, IB, p): the communication-avoiding factorization with p
+    row domains (qr_factor_ca); None: qr_factor with the table's tiling."""
     import torch
     import paper_1102_5328_amd as tq
     A, Ro, cond = _oracle(M, N, seed)
     K = min(M, N)
     tq.tune_load(TABLE)
-    nb, ib, _ = tq.tune(M, N, 1)
+    if tree is None:
+        nb, ib, _ = tq.tune(M, N, 1)
+        p = 1
+    else:
+        nb, ib, p = tree
     with grid_units(units) as cus:
         A0 = tq.colmajor(M, N)
         A0.copy_(torch.from_numpy(A))
         dA = tq.colmajor(M, N)
         dA.copy_(A0)
-        _, T, _, _ = tq.factor(dA, nb, ib)
+        _, T = tq.factor_ca(dA, nb, ib, p)
         tq.sync()
         # invariants on the device: Q^T A vs R, orthogonality sketch
         B = tq.colmajor(M, N)
         B.copy_(A0)
-        tq.apply_Qt(dA, T, nb, ib, B)
+        tq.apply_Qt_ca(dA, T, nb, ib, p, B)
         g = torch.Generator(device="cuda")
         g.manual_seed(seed + 7)
         X = torch.randn((8, M), dtype=torch.float64, device="cuda", generator=g).t()
         Y = tq.colmajor(M, 8)
         Y.copy_(X)
-        tq.apply_Qt(dA, T, nb, ib, Y)
+        tq.apply_Qt_ca(dA, T, nb, ib, p, Y)
         tq.sync()
         Rg_dev = torch.triu(dA[:K])
         E = B.clone()
@@ -82,7 +89,7 @@ def _gpu_check(M, N, seed, units):
     r_rel = float(np.linalg.norm(D) / np.linalg.norm(Ro))
     emax = float(np.abs(D).max())
     bound = oracle.invariant_bound(M, N)
-    out = dict(M=M, N=N, nb=nb, ib=ib, units=cus, cond=cond, r_rel=r_rel,
+    out = dict(M=M, N=N, nb=nb, ib=ib, p=p, units=cus, cond=cond, r_rel=r_rel,
                r_bound=1e-10 * cond, emax=emax, e_bound=bound * nA,
                resid=resid, orth=orth, bound=bound)
     print(out, flush=True)
@@ -94,17 +101,20 @@ def _gpu_check(M, N, seed, units):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("M,N,units", [
-    (2048, 2048, 0),
-    (4096, 4096, 0),
-    (4096, 4096, None),
-    (8192, 8192, 0),
-    (16384, 16384, 0),
-    (16384, 16384, None),
-    (65536, 256, 0),
-    (65536, 1024, 0),
-    (16384, 4096, 0),
-    (2048, 8192, 0),
+@pytest.mark.parametrize("M,N,units,tree", [
+    (2048, 2048, 0, None),
+    (4096, 4096, 0, None),
+    (4096, 4096, None, None),
+    (8192, 8192, 0, None),
+    (16384, 16384, 0, None),
+    (16384, 16384, None, None),
+    (65536, 256, 0, None),
+    (65536, 256, None, (128, 16, 256)),   # the tree: 256 domains of 2 tile rows
+    (65536, 1024, 0, None),
+    (65536, 1024, None, (128, 16, 128)),  # 128 domains of 4 tile rows
+    (16384, 4096, 0, None),
+    (16384, 4096, None, (128, 32, 16)),
+    (2048, 8192, 0, None),
 ])
-def test_fullsize_R_matches_oracle(M, N, units):
-    _gpu_check(M, N, 0, units)
+def test_fullsize_R_matches_oracle(M, N, units, tree):
+    _gpu_check(M, N, 0, units, tree)
