@@ -135,6 +135,36 @@ int qr_factor_ca(double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, i
 int qr_apply_Qt_ca(const double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, int p,
                    const double *T, double *B, int64_t nrhs, int64_t ldb, void *stream);
 
+/* ---------------------------------------------------------------------- */
+/* On top of (V, T): Q itself, B <- Q B, least squares (Section 2.1: Q is */
+/* the product of the block reflectors the factorization stored)          */
+/* ---------------------------------------------------------------------- */
+
+/* B <- Q B with Q from qr_factor_ca(A, M, N, lda, NB, IB, p, T) (p = 1:
+ * qr_factor): the reflectors of the Q^T application in the opposite order,
+ * each block reflector I - V T V^T instead of its transpose. Arguments and
+ * errors as qr_apply_Qt_ca (qr_apply_Q: as qr_apply_Qt, flat tree). */
+int qr_apply_Q_ca(const double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, int p,
+                  const double *T, double *B, int64_t nrhs, int64_t ldb, void *stream);
+int qr_apply_Q(const double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB,
+               const double *T, double *B, int64_t nrhs, int64_t ldb, void *stream);
+
+/* The first k columns of Q (0 <= k <= M) explicitly: Q (out, device, M x k,
+ * ldq >= max(1, M)) <- Q [I_k; 0]. A and T as in qr_apply_Q_ca. Errors as
+ * qr_apply_Q_ca for A .. T, then -9 Q null (with M*k > 0), -10 k, -11 ldq. */
+int qr_form_Q_ca(const double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, int p,
+                 const double *T, double *Q, int64_t k, int64_t ldq, void *stream);
+
+/* Least squares min ||A X - B|| for M >= N from the factorization: B (in/out,
+ * device, M x nrhs, ldb >= max(1, M)) <- Q^T B, then its first N rows <-
+ * R^-1 (Q^T B)[0:N] (back substitution with the upper triangle of A, one
+ * workgroup per right-hand side). On exit rows 0..N-1 of B hold X and rows
+ * N..M-1 the residual's coordinates Q^T (B - A X) (their norm is the
+ * residual norm). A rank-deficient R (a zero diagonal entry) gives Inf/NaN.
+ * Errors as qr_apply_Qt_ca; -3 also for N > M. */
+int qr_solve_ls_ca(const double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, int p,
+                   const double *T, double *B, int64_t nrhs, int64_t ldb, void *stream);
+
 /* Many independent factorizations of uneven sizes in ONE persistent launch
  * over the union of their DAGs, each matrix with its own (NB, IB); the
  * launch is captured in a hipGraph the first time a given batch (pointers,
@@ -314,8 +344,8 @@ double qr_flops(int64_t M, int64_t N);
 double qr_flops_executed(int64_t M, int64_t N, int NB, int IB);
 
 /* Builds the ticket order (as qr_factor_ca / qr_apply_Qt_ca would with p row
- * domains, for `workers` persistent workgroups; apply != 0 for the apply with
- * nrhs columns) and
+ * domains, for `workers` persistent workgroups; apply = 1 for the Q^T apply
+ * with nrhs columns, 2 for the Q apply) and
  * checks it on the host: *seq = waits not yet satisfied when tasks run one
  * at a time in ticket order; *stress = data hazards (program-order
  * violations) seen in a randomised parallel replay with `workers` workers

@@ -119,6 +119,19 @@ void oracle_apply_q(int64_t m, int64_t k, const double *v, int64_t ldv,
         apply_reflector(m, v, ldv, j, tau[j], b, ldb, 0, nrhs);
 }
 
+/* Back substitution: X = R^{-1} B for the upper triangle of the n x n block
+ * R, in place in B (n x nrhs), row n-1 first:
+ * x_i = (b_i - sum_{c>i} R[i][c] x_c) / R[i][i]. */
+void oracle_trsv_upper(int64_t n, const double *r, int64_t ldr, int64_t nrhs, double *b,
+                       int64_t ldb) {
+    for (int64_t q = 0; q < nrhs; ++q)
+        for (int64_t i = n - 1; i >= 0; --i) {
+            double s = IDX(b, i, q, ldb);
+            for (int64_t c = i + 1; c < n; ++c) s -= IDX(r, i, c, ldr) * IDX(b, c, q, ldb);
+            IDX(b, i, q, ldb) = s / IDX(r, i, i, ldr);
+        }
+}
+
 /* Compact-WY factor of the reflectors j0 .. j0+k-1 stored in V (unit entry
  * at row j, tail below it): H_{j0} ... H_{j0+k-1} = I - Vb T Vb^T with T
  * k-by-k upper triangular, T[c][c] = tau_c and

@@ -9,6 +9,7 @@ Functions mirror the plain definitions in oracle.c:
   apply_qt(V, tau, B) -> Q^T B    (reflectors one at a time, ascending)
   apply_q(V, tau, B)  -> Q B      (descending)
   form_q(V, tau, M, K)-> thin Q, M x K
+  trsv_upper(R, B)    -> R^{-1} B (back substitution), lstsq(A, B) -> X, Q^T B
   larft(V, tau, j0,k) -> compact-WY T of reflectors j0..j0+k-1
   gram_entry(A, i, j) -> (A^T A)_ij
   mlp_forward / mlp_grad (FP64 chain rule for the 5-64-64-64-1 ReLU MLP)
@@ -54,6 +55,7 @@ def _load():
     lib.oracle_apply_qt.argtypes = [i64, i64, dp, i64, dp, i64, dp, i64]
     lib.oracle_apply_q.argtypes = [i64, i64, dp, i64, dp, i64, dp, i64]
     lib.oracle_larft.argtypes = [i64, i64, i64, dp, i64, dp, dp, i64]
+    lib.oracle_trsv_upper.argtypes = [i64, dp, i64, i64, dp, i64]
     lib.oracle_gram_entry.argtypes = [i64, dp, i64, i64, i64]
     lib.oracle_gram_entry.restype = dbl
     lib.oracle_mlp_forward.argtypes = [dp, dp, i64, dp]
@@ -124,6 +126,26 @@ def form_q(VR, tau, ncols=None):
     e = np.zeros((m, ncols), dtype=np.float64, order="F")
     e[np.arange(min(m, ncols)), np.arange(min(m, ncols))] = 1.0
     return apply_q(VR, tau, e)
+
+
+def trsv_upper(R, B):
+    """R^{-1} B for the upper triangle of the square R (back substitution)."""
+    r = np.asfortranarray(R, dtype=np.float64)
+    b = _fortran(B if B.ndim == 2 else B.reshape(-1, 1))
+    n = r.shape[0]
+    _load().oracle_trsv_upper(n, _p(r), max(1, n), b.shape[1], _p(b), max(1, n))
+    return b
+
+
+def lstsq(A, B):
+    """Least-squares solution of A X = B for M >= N and full column rank:
+    with A = QR, X = R^{-1} (Q^T B)[0:N] (the unique minimiser; Section 2.1's
+    Q and R). Returns (X, Q^T B)."""
+    M, N = A.shape
+    VR, tau = geqr2(A)
+    QtB = apply_qt(VR, tau, B)
+    X = trsv_upper(np.asfortranarray(VR[:N, :N]), np.asfortranarray(QtB[:N]))
+    return X, QtB
 
 
 def larft(VR, tau, j0, k):

@@ -145,6 +145,41 @@ def apply_Qt_ca(A, T, nb, ib, p, B, stream=None):
     return B
 
 
+def apply_Q(A, T, nb, ib, B, p=1, stream=None):
+    """B <- Q B in place (qr_apply_Q_ca; same nb, ib, p as the factorization)."""
+    M, N = A.shape
+    _ensure_table()
+    check(_lib.lib().qr_apply_Q_ca(ctypes.c_void_p(A.data_ptr()), M, N, _ld(A), nb, ib, p,
+                                   ctypes.c_void_p(T.data_ptr()), ctypes.c_void_p(B.data_ptr()),
+                                   B.shape[1], _ld(B), _stream(stream)), "qr_apply_Q_ca")
+    return B
+
+
+def form_Q(A, T, nb, ib, k=None, p=1, Q=None, stream=None):
+    """The first k columns of Q (default min(M, N)) as an M x k column-major
+    tensor (qr_form_Q_ca)."""
+    M, N = A.shape
+    k = min(M, N) if k is None else k
+    if Q is None:
+        Q = colmajor(M, k, device=A.device)
+    _ensure_table()
+    check(_lib.lib().qr_form_Q_ca(ctypes.c_void_p(A.data_ptr()), M, N, _ld(A), nb, ib, p,
+                                  ctypes.c_void_p(T.data_ptr()), ctypes.c_void_p(Q.data_ptr()),
+                                  k, _ld(Q), _stream(stream)), "qr_form_Q_ca")
+    return Q
+
+
+def solve_ls(A, T, nb, ib, B, p=1, stream=None):
+    """Least squares for M >= N in place: B <- [X; Q^T residual] with X in
+    the first N rows (qr_solve_ls_ca)."""
+    M, N = A.shape
+    _ensure_table()
+    check(_lib.lib().qr_solve_ls_ca(ctypes.c_void_p(A.data_ptr()), M, N, _ld(A), nb, ib, p,
+                                    ctypes.c_void_p(T.data_ptr()), ctypes.c_void_p(B.data_ptr()),
+                                    B.shape[1], _ld(B), _stream(stream)), "qr_solve_ls_ca")
+    return B
+
+
 def factor_noalloc(A, nb, ib, T, stream=None):
     """qr_factor_noalloc: the factorization without device allocations (T
     supplied by the caller; the library's static scratch holds the rest)."""

@@ -31,6 +31,10 @@ SIGNATURES = {
     "qr_T_size_ca": (c_i64, [c_i64, c_i64, c_int, c_int, c_int]),
     "qr_factor_ca": (c_int, [c_vp, c_i64, c_i64, c_i64, c_int, c_int, c_int, c_vp, c_vp]),
     "qr_apply_Qt_ca": (c_int, [c_vp, c_i64, c_i64, c_i64, c_int, c_int, c_int, c_vp, c_vp, c_i64, c_i64, c_vp]),
+    "qr_apply_Q_ca": (c_int, [c_vp, c_i64, c_i64, c_i64, c_int, c_int, c_int, c_vp, c_vp, c_i64, c_i64, c_vp]),
+    "qr_apply_Q": (c_int, [c_vp, c_i64, c_i64, c_i64, c_int, c_int, c_vp, c_vp, c_i64, c_i64, c_vp]),
+    "qr_form_Q_ca": (c_int, [c_vp, c_i64, c_i64, c_i64, c_int, c_int, c_int, c_vp, c_vp, c_i64, c_i64, c_vp]),
+    "qr_solve_ls_ca": (c_int, [c_vp, c_i64, c_i64, c_i64, c_int, c_int, c_int, c_vp, c_vp, c_i64, c_i64, c_vp]),
     "qr_factor": (c_int, [c_vp, c_i64, c_i64, c_i64, c_int, c_int, c_vp, c_vp]),
     "qr_factor_noalloc": (c_int, [c_vp, c_i64, c_i64, c_i64, c_int, c_int, c_vp, c_vp]),
     "qr_apply_Qt": (c_int, [c_vp, c_i64, c_i64, c_i64, c_int, c_int, c_vp, c_vp, c_i64, c_i64, c_vp]),

@@ -30,6 +30,13 @@ hipError_t tq_launch_persistent(const TqLaunch &a, hipStream_t st);
 int tq_occupancy(size_t lds_bytes);
 hipError_t tq_launch_ssrfb_bench(double *buf, int nb, int ib, int calls, int grid, hipStream_t st);
 hipError_t tq_launch_fill(double *p, int64_t n, uint64_t seed, double scale, hipStream_t st);
+// Q (M x k, leading dimension ldq) <- the first k columns of the identity.
+hipError_t tq_launch_eye(double *Q, int64_t M, int64_t k, int64_t ldq, hipStream_t st);
+// B[0:N, 0:nrhs] <- R^-1 B[0:N, 0:nrhs] with R the upper triangle of the
+// N x N block at R (leading dimension ldr): back substitution, one workgroup
+// per right-hand side.
+hipError_t tq_launch_trsv_upper(const double *R, int64_t ldr, int64_t N, double *B, int64_t ldb,
+                                int64_t nrhs, hipStream_t st);
 
 // Allocation-free factorization (qr_factor_noalloc): a static device array
 // of TQ_NOALLOC_SCRATCH_INTS ints per device; int 0 is the error word, int 1

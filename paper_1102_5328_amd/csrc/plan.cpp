@@ -23,6 +23,7 @@ void md_init(MatDesc &md, int64_t M, int64_t N, int nb, int ib, int w, int64_t n
   const int pp = p < 1 ? 1 : (p > md.MT ? (md.MT > 0 ? md.MT : 1) : p);
   md.h = md.MT > 0 ? (md.MT + pp - 1) / pp : 1;
   md.D = md.MT > 0 ? (md.MT + md.h - 1) / md.h : 1;
+  md.notrans = 0;
 }
 
 void tree_step(const MatDesc &md, int k, std::vector<int> &heads, std::vector<int> &rest,
@@ -54,6 +55,7 @@ void enum_factor_tasks(const MatDesc &md, int mat, std::vector<Task> &out) {
 
 void enum_apply_tasks(const MatDesc &md, int mat, std::vector<Task> &out) {
   std::vector<int> heads, rest, bottoms;
+  const size_t first = out.size();
   for (int k = 0; k < md.KT; ++k) {
     tree_step(md, k, heads, rest, bottoms);
     const int types[3] = {TK_LARFB_B, TK_SSRFB_B, TK_TTMQR_B};
@@ -62,6 +64,8 @@ void enum_apply_tasks(const MatDesc &md, int mat, std::vector<Task> &out) {
       for (int i : *rows[q])
         for (int s = 0; s < md.SB; ++s) out.push_back(make_task(types[q], mat, i, 0, k, s));
   }
+  // B <- Q B: the reflectors in the opposite order
+  if (md.notrans) std::reverse(out.begin() + first, out.end());
 }
 
 void dag_tile_counts(int64_t M, int64_t N, int nb, int64_t counts[4]) {

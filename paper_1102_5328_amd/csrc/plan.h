@@ -21,7 +21,7 @@ void tree_step(const MatDesc &md, int k, std::vector<int> &heads, std::vector<in
 // the merges in level order, then the LARFBs, SSRFBs and TTMQRs in the same
 // row orders). This order is a topological order of the DAG.
 void enum_factor_tasks(const MatDesc &md, int mat, std::vector<Task> &out);
-void enum_apply_tasks(const MatDesc &md, int mat, std::vector<Task> &out);
+void enum_apply_tasks(const MatDesc &md, int mat, std::vector<Task> &out);  // reversed if md.notrans
 
 // Counts of GEQRT / TSQRT / LARFB / SSRFB tile tasks (strips not split).
 void dag_tile_counts(int64_t M, int64_t N, int nb, int64_t counts[4]);

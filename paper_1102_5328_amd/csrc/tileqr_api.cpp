@@ -526,8 +526,9 @@ int qr_factor_noalloc(double *A, int64_t M, int64_t N, int64_t lda, int NB, int 
   return 0;
 }
 
-int qr_apply_Qt_ca(const double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, int p,
-                   const double *T, double *B, int64_t nrhs, int64_t ldb, void *stream) {
+static int apply_impl(const double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, int p,
+                      const double *T, double *B, int64_t nrhs, int64_t ldb, void *stream,
+                      bool notrans) {
   if (M < 0) return -2;
   if (N < 0) return -3;
   if (!A && M * N > 0) return -1;
@@ -556,7 +557,8 @@ int qr_apply_Qt_ca(const double *A, int64_t M, int64_t N, int64_t lda, int NB, i
   if ((int64_t)md.SB > 4095) return TILEQR_ERR_TOO_LARGE;
   md.lda = lda;
   md.ldb = ldb;
-  PlanKey key{0, 1, NB, IB, M, N, nrhs, 0};
+  md.notrans = notrans ? 1 : 0;
+  PlanKey key{0, notrans ? 2 : 1, NB, IB, M, N, nrhs, 0};
   key.cus = units_for(M, N, 1);
   key.h = md.h;
   hipGetDevice(&key.dev);
@@ -568,6 +570,48 @@ int qr_apply_Qt_ca(const double *A, int64_t M, int64_t N, int64_t lda, int NB, i
   md.ctr = 0;
   TqLaunch a = make_launch(*pl, *ds, md);
   if (tq_launch_persistent(a, (hipStream_t)stream) != hipSuccess) return TILEQR_ERR_HIP;
+  return 0;
+}
+
+int qr_apply_Qt_ca(const double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, int p,
+                   const double *T, double *B, int64_t nrhs, int64_t ldb, void *stream) {
+  return apply_impl(A, M, N, lda, NB, IB, p, T, B, nrhs, ldb, stream, false);
+}
+
+int qr_apply_Q_ca(const double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, int p,
+                  const double *T, double *B, int64_t nrhs, int64_t ldb, void *stream) {
+  return apply_impl(A, M, N, lda, NB, IB, p, T, B, nrhs, ldb, stream, true);
+}
+
+int qr_apply_Q(const double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB,
+               const double *T, double *B, int64_t nrhs, int64_t ldb, void *stream) {
+  const int rc = qr_apply_Q_ca(A, M, N, lda, NB, IB, 1, T, B, nrhs, ldb, stream);
+  return rc <= -8 ? rc + 1 : rc;
+}
+
+int qr_form_Q_ca(const double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, int p,
+                 const double *T, double *Q, int64_t k, int64_t ldq, void *stream) {
+  if (k < 0 || k > M) return -10;
+  if (!Q && M * k > 0) return -9;
+  if (ldq < std::max<int64_t>(1, M)) return -11;
+  // the argument checks of the apply come first: nothing is written on error
+  int rc = apply_impl(A, M, N, lda, NB, IB, p, T, nullptr, 0, std::max<int64_t>(1, M), stream,
+                      true);
+  if (rc) return rc;
+  if (M == 0 || k == 0) return 0;
+  if (tq_launch_eye(Q, M, k, ldq, (hipStream_t)stream) != hipSuccess) return TILEQR_ERR_HIP;
+  if (N == 0) return 0;
+  return apply_impl(A, M, N, lda, NB, IB, p, T, Q, k, ldq, stream, true);
+}
+
+int qr_solve_ls_ca(const double *A, int64_t M, int64_t N, int64_t lda, int NB, int IB, int p,
+                   const double *T, double *B, int64_t nrhs, int64_t ldb, void *stream) {
+  if (N > M) return -3;
+  int rc = apply_impl(A, M, N, lda, NB, IB, p, T, B, nrhs, ldb, stream, false);
+  if (rc) return rc;
+  if (N == 0 || nrhs == 0) return 0;
+  if (tq_launch_trsv_upper(A, lda, N, B, ldb, nrhs, (hipStream_t)stream) != hipSuccess)
+    return TILEQR_ERR_HIP;
   return 0;
 }
 
@@ -1125,6 +1169,7 @@ int qr_plan_check(int64_t M, int64_t N, int NB, int IB, int p, int64_t nrhs, int
   MatDesc md;
   std::memset(&md, 0, sizeof(md));
   md_setup(md, M, N, NB, IB, apply ? nrhs : 0, p);
+  md.notrans = apply == 2 ? 1 : 0;
   md.ctr = 0;
   std::vector<MatDesc> mats{md};
   std::vector<Task> order;
@@ -1143,6 +1188,7 @@ int qr_plan_tasks(int64_t M, int64_t N, int NB, int IB, int p, int64_t nrhs, int
   MatDesc md;
   std::memset(&md, 0, sizeof(md));
   md_setup(md, M, N, NB, IB, apply ? nrhs : 0, p);
+  md.notrans = apply == 2 ? 1 : 0;
   md.ctr = 0;
   std::vector<MatDesc> mats{md};
   std::vector<Task> order;

@@ -411,27 +411,32 @@ __device__ inline void update_group(const Lds &L, int kind, int s, int q0, int n
   }
 }
 
-// W = T_s^T Ytot in place in the group region, bottom block first (W block q
-// needs Y blocks <= q). T_s from the LDS stage or from global memory.
+// W = T_s^T Ytot (or T_s Ytot when notrans) in place in the group region:
+// W block q needs the Y blocks <= q (>= q), so the blocks go bottom (top)
+// first. T_s from the LDS stage or from global memory.
 template <bool TLDS>
 __device__ inline void w_phase(const Lds &L, const double *Ts, int64_t ldt, int ibw, int ldts,
-                               ldbl *yw) {
+                               ldbl *yw, bool notrans = false) {
   const gdbl *Tg = gp(Ts);
   const int ln = lane_id();
   const int nq = (ibw + 15) >> 4;
-  for (int q = nq - 1; q >= 0; --q) {
+  for (int qi = 0; qi < nq; ++qi) {
+    const int q = notrans ? qi : nq - 1 - qi;
     d4 w = {0.0, 0.0, 0.0, 0.0};
-    const int ccol = q * 16 + (ln & 15);
-    for (int q2 = 0; q2 <= q; ++q2) {
+    const int orow = q * 16 + (ln & 15);  // output row of W
+    const int q2lo = notrans ? q : 0, q2hi = notrans ? nq - 1 : q;
+    for (int q2 = q2lo; q2 <= q2hi; ++q2) {
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
-        const int arow = q2 * 16 + 4 * kk + (ln >> 4);
+        const int kr = q2 * 16 + 4 * kk + (ln >> 4);  // contraction index
+        // transposed: T[kr][orow]; not transposed: T[orow][kr] (upper)
+        const int tr = notrans ? orow : kr, tc = notrans ? kr : orow;
         double a;
         if (TLDS)
-          a = L.ts[arow * ldts + ccol];
+          a = L.ts[tr * ldts + tc];
         else
-          a = (arow <= ccol && ccol < ibw) ? Tg[arow + (int64_t)ccol * ldt] : 0.0;
-        w = mfma(a, yw[arow * 16 + (ln & 15)], w);
+          a = (tr <= tc && tc < ibw) ? Tg[tr + (int64_t)tc * ldt] : 0.0;
+        w = mfma(a, yw[kr * 16 + (ln & 15)], w);
       }
     }
     wave_sync();
@@ -479,7 +484,7 @@ template <int RW>
 __device__ __forceinline__ void apply_strip(const Lds &L, const double *V, int64_t ldv, int vrows,
                                             int kind, int kref, int ib, const double *T,
                                             int64_t ldt, double *C1, int64_t ldc1, double *C2,
-                                            int64_t ldc2, int ncols) {
+                                            int64_t ldc2, int ncols, bool notrans) {
   constexpr int ROWS = Geo<RW>::ROWS;
   const int ln = lane_id(), wv = wave_id();
   const int cg = wv / RW, rb = wv % RW, rbase = rb * TQ_ROWS_PER_WAVE;
@@ -491,7 +496,7 @@ __device__ __forceinline__ void apply_strip(const Lds &L, const double *V, int64
   const int nqb = ibp >> 4;
   // Register pipeline: the whole block fits the staged chunks and the
   // prefetch registers, and T_s the LDS stage.
-  const bool pf = tl && nqb <= L.gmax && nqb * 16 * ROWS <= PF * NTHR;
+  const bool pf = tl && nqb <= L.gmax && nqb * 16 * ROWS <= PF * NTHR && !notrans;
   ldbl *yw = L.y + cg * L.ibp * 16;
   const bool c1w = C1 != nullptr && rb == 0 && gact;
   d4 c2[RT];
@@ -503,7 +508,10 @@ __device__ __forceinline__ void apply_strip(const Lds &L, const double *V, int64
     tstage_load(pt, T, ldt, ibw0);
     if (c1w) c1_load(pc, C1, ldc1, 0, ibw0, ncols, cg);
   }
-  for (int s = 0; s < kref; s += ib) {
+  const int nblk = (kref + ib - 1) / ib;
+  for (int bi = 0; bi < nblk; ++bi) {
+    // Q^T: blocks in order; Q: the last block first
+    const int s = (notrans ? nblk - 1 - bi : bi) * ib;
     const int ibw = min(ib, kref - s);
     const int nq = (ibw + 15) >> 4;
     const bool resident = nq <= L.gmax;
@@ -556,9 +564,9 @@ __device__ __forceinline__ void apply_strip(const Lds &L, const double *V, int64
     if (rb == 0 && gact) {
       wave_sync();
       if (tl)
-        w_phase<true>(L, nullptr, 0, ibw, ldts, yw);
+        w_phase<true>(L, nullptr, 0, ibw, ldts, yw, notrans);
       else
-        w_phase<false>(L, T + (int64_t)s * ldt, ldt, ibw, ldts, yw);
+        w_phase<false>(L, T + (int64_t)s * ldt, ldt, ibw, ldts, yw, notrans);
     }
     if (c1w) {
       if (pf) {
@@ -727,7 +735,7 @@ template <int RW>
 __device__ __forceinline__ void apply_cols(const Lds &L, const double *V, int64_t ldv, int vrows,
                                            int kind, int kref, int ib, const double *T,
                                            int64_t ldt, double *C1, int64_t ldc1, double *C2,
-                                           int64_t ldc2, int ncols) {
+                                           int64_t ldc2, int ncols, bool notrans = false) {
   constexpr int w = Geo<RW>::P;
   for (int c0 = 0; c0 < ncols; c0 += w) {
     double *c1 = C1 ? C1 + (int64_t)c0 * ldc1 : nullptr;
@@ -735,13 +743,13 @@ __device__ __forceinline__ void apply_cols(const Lds &L, const double *V, int64_
     const int nc = min(w, ncols - c0);
     // uniform choice of the straight-line form
     const bool fast = RW == 1 && vrows == TQ_ROWS_PER_WAVE && nc == w && kref % ib == 0 &&
-                      L.gmax * 16 >= ib;
+                      L.gmax * 16 >= ib && !notrans;
     if (fast && ib == 32)
       apply_strip_fast<32>(L, V, ldv, kind, kref, T, ldt, c1, ldc1, c2, ldc2);
     else if (fast && ib == 16)
       apply_strip_fast<16>(L, V, ldv, kind, kref, T, ldt, c1, ldc1, c2, ldc2);
     else
-      apply_strip<RW>(L, V, ldv, vrows, kind, kref, ib, T, ldt, c1, ldc1, c2, ldc2, nc);
+      apply_strip<RW>(L, V, ldv, vrows, kind, kref, ib, T, ldt, c1, ldc1, c2, ldc2, nc, notrans);
   }
   __syncthreads();
 }
@@ -1261,7 +1269,8 @@ __device__ __forceinline__ void run_task(const Task &t, const MatDesc &m, const 
     aC2 = At(i, j) + (int64_t)c0 * lda;
     if (!larfb) aC1 = At(top, j) + (int64_t)c0 * lda;
   }
-  apply_cols<RW>(L, aV, ldv, vrows, kind, kref, ib, aT, ib, aC1, ldc, aC2, ldc, ncols);
+  apply_cols<RW>(L, aV, ldv, vrows, kind, kref, ib, aT, ib, aC1, ldc, aC2, ldc, ncols,
+                 onB && m.notrans);
 }
 
 // The task's matrix descriptor, field by field from the batch array or the
@@ -1292,6 +1301,7 @@ __device__ __forceinline__ MatDesc load_desc(const MatDesc *__restrict__ mats, i
   m.gmax = g->gmax;
   m.h = g->h;
   m.D = g->D;
+  m.notrans = g->notrans;
   return m;
 }
 
@@ -1465,6 +1475,39 @@ __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
 }
 
 // Deterministic fill with values in [-scale, scale] (splitmix64 hash).
+// Q <- [I_k; 0] (M x k).
+__global__ void tq_eye(double *Q, int64_t M, int64_t k, int64_t ldq) {
+  const int64_t total = M * k;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e % M, c = e / M;
+    Q[r + c * ldq] = r == c ? 1.0 : 0.0;
+  }
+}
+
+// Back substitution R x = b for one right-hand side per workgroup (column
+// blockIdx.x of B), a column of R at a time: x_j = b_j / R_jj, then
+// b[0:j] -= x_j R[0:j, j] by all threads.
+__global__ __launch_bounds__(NTHR) void tq_trsv_upper(const double *R, int64_t ldr, int64_t N,
+                                                      double *B, int64_t ldb) {
+  gdbl *b = gp(B) + (int64_t)blockIdx.x * ldb;
+  const gdbl *Rg = gp(R);
+  const int tid = threadIdx.x;
+  __shared__ double s_x;
+  for (int64_t j = N - 1; j >= 0; --j) {
+    if (tid == 0) {
+      const double x = b[j] / Rg[j + j * ldr];
+      b[j] = x;
+      s_x = x;
+    }
+    __syncthreads();
+    const double x = s_x;
+    const gdbl *rc = Rg + j * ldr;
+    for (int64_t i = tid; i < j; i += NTHR) b[i] -= x * rc[i];
+    __syncthreads();
+  }
+}
+
 __global__ void tq_fill_hash(double *p, int64_t n, uint64_t seed, double scale) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -1521,6 +1564,21 @@ hipError_t tq_launch_ssrfb_bench(double *buf, int nb, int ib, int calls, int gri
   hipError_t e = set_lds((const void *)tq_ssrfb_bench, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(tq_ssrfb_bench, dim3(grid), dim3(NTHR), lds, st, buf, m, calls);
+  return hipGetLastError();
+}
+
+hipError_t tq_launch_eye(double *Q, int64_t M, int64_t k, int64_t ldq, hipStream_t st) {
+  if (M <= 0 || k <= 0) return hipSuccess;
+  int64_t g = (M * k + 255) / 256;
+  g = g > 4096 ? 4096 : g;
+  hipLaunchKernelGGL(tq_eye, dim3((unsigned)g), dim3(256), 0, st, Q, M, k, ldq);
+  return hipGetLastError();
+}
+
+hipError_t tq_launch_trsv_upper(const double *R, int64_t ldr, int64_t N, double *B, int64_t ldb,
+                                int64_t nrhs, hipStream_t st) {
+  if (N <= 0 || nrhs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(tq_trsv_upper, dim3((unsigned)nrhs), dim3(NTHR), 0, st, R, ldr, N, B, ldb);
   return hipGetLastError();
 }
 

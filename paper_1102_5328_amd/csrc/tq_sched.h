@@ -97,6 +97,7 @@ struct MatDesc {
   int32_t gmax;  // V chunks staged in LDS at once
   int32_t h;     // tile rows per domain (>= MT: flat tree)
   int32_t D;     // domains, ceil(MT / h)
+  int32_t notrans;  // apply: B <- Q B (the Q^T program reversed) instead of Q^T B
 };
 
 TQ_HD inline int tile_rows(const MatDesc &m, int i) {
@@ -162,6 +163,16 @@ TQ_HD inline int tree_writes_before(const MatDesc &m, int i, int k) {
   return w;
 }
 
+// Writes to B's tile row i over the whole Q^T application: one per earlier
+// step, and, for a row that becomes a diagonal row (i < KT), the root head's
+// writes at step i (its LARFB, the SSRFBs of its domain, its merges).
+TQ_HD inline int tree_writes_total(const MatDesc &m, int i) {
+  const int kk = tq_min(i, m.KT);
+  int w = tree_writes_before(m, i, kk);
+  if (i < m.KT) w += tree_rows(m, i / m.h, i) + tree_tops(0, m.D - i / m.h, 31);
+  return w;
+}
+
 // Storage of the merges' reflectors and T factors after the per-tile T:
 // (k, d) -> nb x nb block and ib x nb block.
 TQ_HD inline int64_t tile_T_doubles(const MatDesc &m) {
@@ -223,9 +234,10 @@ TQ_HD inline int task_nwaits(const Task &t, const MatDesc &m) {
   return 0;
 }
 
-TQ_HD inline void task_wait(const Task &t, const MatDesc &m, int q, int64_t *idx,
-                            int *target) {
+TQ_HD inline void task_wait_fwd(const Task &t, const MatDesc &m, int q, int64_t *idx,
+                                int *target, int *row) {
   const int i = t.i, j = t.j, k = t.k, s = task_strip(t);
+  *row = i;
   const int type = task_type(t);
   switch (type) {
     case TK_GEQRT:  // every strip of A_ik has received its earlier updates
@@ -301,6 +313,7 @@ TQ_HD inline void task_wait(const Task &t, const MatDesc &m, int q, int64_t *idx
       if (q == 0) {
         *idx = ctr_verB(m, hd, s);
         *target = tree_writes_before(m, hd, k) + i - hd;
+        *row = hd;
       } else {
         *idx = ctr_verB(m, i, s);
         *target = k;
@@ -313,6 +326,7 @@ TQ_HD inline void task_wait(const Task &t, const MatDesc &m, int q, int64_t *idx
       if (q == 0) {
         *idx = ctr_verB(m, i1, s);
         *target = tree_writes_before(m, i1, k) + tree_top_before(m, i1, k, l);
+        *row = i1;
       } else {
         *idx = ctr_verB(m, i, s);
         *target = tree_writes_before(m, i, k) + tree_bottom_before(m, i, k);
@@ -320,6 +334,15 @@ TQ_HD inline void task_wait(const Task &t, const MatDesc &m, int q, int64_t *idx
       return;
     }
   }
+}
+
+// The wait in the program actually run: for B <- Q B the Q^T program runs
+// backwards, so a task waits for the writes that follow it in the forward
+// order.
+TQ_HD inline void task_wait(const Task &t, const MatDesc &m, int q, int64_t *idx, int *target) {
+  int row;
+  task_wait_fwd(t, m, q, idx, target, &row);
+  if (m.notrans && task_on_B(task_type(t))) *target = tree_writes_total(m, row) - *target - 1;
 }
 
 // Signals: number, then the q-th counter index to increment.

@@ -121,7 +121,13 @@ int main(int argc, char **argv) {
     double r = (i <= j && i < K) ? A[i + (size_t)j * lda] : 0.0;
     double d = B[i + (size_t)j * lda] - r; rn += d * d; an += A0[i + (size_t)j * lda] * A0[i + (size_t)j * lda];
   }
-  const double rrel = sqrt(num / den), res = sqrt(rn / an);
-  printf("M=%d N=%d nb=%d ib=%d p=%d (h=%d)  R_rel=%.3e  resid=%.3e\n", M, N, nb, ib, p, md.h, rrel, res);
-  return (rrel < 1e-12 && res < 1e-13) ? 0 : 1;
+  // Q (Q^T A0) = A0 via the emulated reverse application
+  md.notrans = 1;
+  if (run({md}, true, 1)) return 1;
+  double qn = 0;
+  for (size_t e = 0; e < B.size(); ++e) qn += (B[e] - A0[e]) * (B[e] - A0[e]);
+  const double rrel = sqrt(num / den), res = sqrt(rn / an), qres = sqrt(qn / an);
+  printf("M=%d N=%d nb=%d ib=%d p=%d (h=%d)  R_rel=%.3e  resid=%.3e  QQt=%.3e\n", M, N, nb, ib, p,
+         md.h, rrel, res, qres);
+  return (rrel < 1e-12 && res < 1e-13 && qres < 1e-13) ? 0 : 1;
 }

@@ -102,6 +102,29 @@ def test_ca_argument_errors(lib):
     assert lib.qr_T_size_ca(8, 4, 64, 16, -1) == -5
 
 
+def test_q_and_ls_argument_errors(lib):
+    # qr_apply_Q(_ca), qr_form_Q_ca, qr_solve_ls_ca: every check before any
+    # device call
+    p = ctypes.c_void_p(16)
+    f = lib.qr_apply_Q_ca
+    assert f(None, 8, 4, 8, 64, 16, 1, p, p, 2, 8, None) == -1
+    assert f(p, 8, 4, 8, 64, 16, -1, p, p, 2, 8, None) == -7
+    assert f(p, 8, 4, 8, 64, 16, 1, None, p, 2, 8, None) == -8
+    assert f(p, 8, 4, 8, 64, 16, 1, p, p, 2, 4, None) == -11
+    g = lib.qr_apply_Q
+    assert g(p, 8, 4, 8, 64, 16, None, p, 2, 8, None) == -7
+    assert g(p, 8, 4, 8, 64, 16, p, p, -2, 8, None) == -9
+    h = lib.qr_form_Q_ca
+    assert h(p, 8, 4, 8, 64, 16, 1, p, p, 9, 8, None) == -10   # k > M
+    assert h(p, 8, 4, 8, 64, 16, 1, p, None, 3, 8, None) == -9
+    assert h(p, 8, 4, 8, 64, 16, 1, p, p, 3, 7, None) == -11
+    assert h(p, 8, 4, 8, 64, 16, 1, None, p, 3, 8, None) == -8
+    ls = lib.qr_solve_ls_ca
+    assert ls(p, 4, 8, 4, 64, 16, 1, p, p, 2, 4, None) == -3    # N > M
+    assert ls(p, 8, 4, 8, 64, 16, 1, p, None, 2, 8, None) == -9
+    assert ls(p, 8, 4, 8, 64, 16, 1, p, p, 2, 3, None) == -11
+
+
 def test_ca_T_size(lib):
     """The T buffer of p domains: the per-tile T factors, then one NB x NB
     reflector block and one IB x NB T factor per (step, domain)."""
@@ -116,6 +139,8 @@ def test_ca_T_size(lib):
 
 
 @pytest.mark.parametrize("M,N,nb,ib,p,workers,apply,nrhs", [
+    (1000, 300, 64, 16, 3, 16, 2, 11),       # B <- Q B: the Q^T program reversed
+    (700, 700, 64, 16, 1, 64, 2, 40),
     (1000, 200, 64, 16, 2, 64, False, 0),
     (1000, 200, 64, 16, 5, 7, False, 0),     # ragged last domain
     (1000, 200, 64, 16, 16, 256, False, 0),  # one row per domain

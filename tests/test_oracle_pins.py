@@ -272,3 +272,43 @@ def test_mlp_forward_hand_computed_negative_preactivations(orc):
     # Row 1 (x0 = 3) has z3_1 < 0, so W3[1][0] gets its gradient from rows
     # 2 and 3 only, where h2_0 = 0: zero in all.
     assert g[W3 + 1 * 64 + 0] == 0.0
+
+
+def test_back_substitution_hand_computed(orc):
+    """A 3x3 upper-triangular system with an integer solution, worked by
+    hand: x3 = 8/4 = 2, x2 = (7 - 1*2)/5 = 1, x1 = (9 - 2*1 - 3*2)/1 = 1."""
+    R = np.array([[1.0, 2.0, 3.0], [0.0, 5.0, 1.0], [0.0, 0.0, 4.0]], order="F")
+    B = np.array([[9.0], [7.0], [8.0]], order="F")
+    X = orc.trsv_upper(R, B)
+    assert np.array_equal(X[:, 0], [1.0, 1.0, 2.0])
+    # the strictly lower part is never read
+    R2 = R.copy(order="F")
+    R2[1, 0], R2[2, 0], R2[2, 1] = np.nan, np.nan, np.nan
+    assert np.array_equal(orc.trsv_upper(R2, B)[:, 0], [1.0, 1.0, 2.0])
+
+
+def test_lstsq_consistent_system_is_exact(orc):
+    """B = A X0 (a consistent system): the least-squares solution is X0 and
+    the residual coordinates Q^T B below row N vanish."""
+    rng = np.random.default_rng(3)
+    A = np.asfortranarray(rng.standard_normal((40, 7)))
+    X0 = rng.standard_normal((7, 3))
+    X, QtB = orc.lstsq(A, np.asfortranarray(A @ X0))
+    assert np.allclose(X, X0, atol=1e-12, rtol=0)
+    assert np.linalg.norm(QtB[7:]) <= 1e-12 * np.linalg.norm(A @ X0)
+
+
+@pytest.mark.parametrize("shape", [(30, 30), (60, 13), (200, 40)])
+def test_lstsq_matches_lapack_and_normal_equations(orc, shape):
+    """Against LAPACK's least squares (numpy.linalg.lstsq, an independent
+    SVD-based solver), and the normal equations A^T (A X - B) = 0; the norm
+    of the rows of Q^T B below N is the residual norm."""
+    rng = np.random.default_rng(shape[0] + shape[1])
+    A = np.asfortranarray(rng.standard_normal(shape))
+    B = np.asfortranarray(rng.standard_normal((shape[0], 2)))
+    X, QtB = orc.lstsq(A, B)
+    Xl = np.linalg.lstsq(A, B, rcond=None)[0]
+    assert np.allclose(X, Xl, atol=1e-10, rtol=0)
+    assert np.linalg.norm(A.T @ (A @ X - B)) <= 1e-10 * np.linalg.norm(A) ** 2 * np.linalg.norm(X)
+    res = np.linalg.norm(A @ X - B, axis=0)
+    assert np.allclose(np.linalg.norm(QtB[shape[1]:], axis=0), res, rtol=1e-10, atol=1e-12)
