@@ -101,6 +101,18 @@ inline int __builtin_amdgcn_mov_dpp(int v, int ctrl, int, int, bool) {
   return r;
 }
 
+// v_readlane_b32: lane `src`'s value to the whole wave (every lane calls it).
+inline int __builtin_amdgcn_readlane(int v, int src) {
+  int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  assert(src >= 0 && src < 64);
+  int *islot = (int *)&g_wave_a[w][0];
+  islot[l] = v;
+  g_wave_bar[w]->arrive_and_wait();
+  int r = islot[src];
+  g_wave_bar[w]->arrive_and_wait();
+  return r;
+}
+
 typedef double emu_d4 __attribute__((ext_vector_type(4)));
 // v_mfma_f64_16x16x4f64 with the assumed lane layout:
 //   A[i][k] in lane i + 16k, B[k][j] in lane j + 16k, D[i][j] in lane j + 16*(i%4), item i/4
