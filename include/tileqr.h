@@ -256,7 +256,9 @@ int qr_ssrfb_bench_flush(int NB, int IB, int calls, int workers, int64_t flush_b
  * +8 when the model was consulted but its ensemble spread exceeded 5 %
  * (the caller should run the pruned search for this shape). The spread is
  * the largest loss, against its own best candidate, that any model of the
- * ensemble predicts for the ensemble-mean choice.
+ * ensemble predicts for the ensemble-mean choice. The model ranks flat-tree
+ * pairs on the whole device, so it is not consulted where the table's entry
+ * carries a row-domain count above 1 or belongs to a compute-unit budget.
  * Errors: -1 M < 0, -2 N < 0, -3 batch < 1, -4 NB null, -5 IB null. */
 int qr_tune(int64_t M, int64_t N, int64_t batch, int *NB, int *IB, int *source);
 

@@ -1033,12 +1033,15 @@ int qr_tune(int64_t M, int64_t N, int64_t batch, int *NB, int *IB, int *source) 
   }
   std::lock_guard<std::mutex> lk(g_mu);
   int nb = g_default_nb, ib = g_default_ib;
-  if (const TableEntry *e = nearest_entry(M, N, batch)) {
+  const TableEntry *e = nearest_entry(M, N, batch);
+  if (e) {
     nb = e->nb;
     ib = e->ib;
     src = 1;
   }
-  if (g_model.nmodels > 0) {
+  // The cost model ranks (NB, IB) pairs of the flat tree on the whole
+  // device: it is consulted only where the table's decision is one of those.
+  if (g_model.nmodels > 0 && !(e && (e->p > 1 || e->budget > 0))) {
     int mnb = 0, mib = 0;
     double spread = 1.0;
     int rc = tq_mlp_choose(g_model.params.data(), g_model.nmodels, g_model.fmean, g_model.fstd,

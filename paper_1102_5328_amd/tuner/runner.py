@@ -33,11 +33,12 @@ def config2_pairs(nbs=(64, 96, 128, 192, 256, 384, 512), ib_min=16, max_nb=ENABL
 def domain_candidates(M, N, nb):
     """Row-domain counts p of the communication-avoiding tree tried for an
     M x N shape with tile order nb: the flat tree (p = 1) and, for tall
-    shapes (M >= 4N, whose panels are long chains), domains of 8, 4, 2 and 1
-    tile rows."""
+    shapes (M >= 16N, whose panels are long chains and whose steps are few),
+    domains of 8, 4, 2 and 1 tile rows. (At M = 4N the merges' per-step
+    synchronisation already costs more than the shorter chains save.)"""
     MT = -(-M // nb)
     out = [1]
-    if M >= 4 * N:
+    if M >= 16 * N:
         for h in (8, 4, 2, 1):
             p = -(-MT // h)
             if p > 1 and p not in out:
