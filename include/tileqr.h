@@ -27,6 +27,11 @@
  *    is invalid; positive: TILEQR_ERR_* below.
  *  - QR has no numerical failure: rank deficiency gives zero diagonal
  *    entries in R; NaN/Inf propagate unchecked.
+ *  - Range: a reflector's norm is formed from the unscaled sum of squares of
+ *    its column (no LAPACK-style rescaling), so entries must stay within
+ *    about 1e-150 .. 1e150 in magnitude: above it the sum overflows, below it
+ *    a nonzero tail can round to a zero norm and be left in place. Scale the
+ *    matrix first when its entries may leave that range.
  */
 #ifndef TILEQR_H
 #define TILEQR_H

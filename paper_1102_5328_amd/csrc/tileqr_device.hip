@@ -366,12 +366,24 @@ __device__ inline void y_group(const Lds &L, int kind, int s, int q0, int ng, in
     for (int r = 0; r < 4; ++r) y[r] = d4{0.0, 0.0, 0.0, 0.0};
     const int rt0 = first_rt(kind, s, q, rbase);
     const ldbl *vp = L.vc + (g * 16 + (ln & 15)) * LDVC + rbase + (ln >> 4);
+    // A operands one row tile ahead of their MFMAs (every read stays inside
+    // the staged column), so the LDS latency hides behind the MFMAs
+    double a[4], an[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a[r] = vp[4 * r];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
+      if (rt + 1 < RT) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) an[r] = vp[(rt + 1) * 16 + 4 * r];
+      }
+      __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
       if (rt >= rt0 && rbase + rt * 16 < vrows) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) y[r] = mfma(vp[rt * 16 + 4 * r], c2[rt][r], y[r]);
+        for (int r = 0; r < 4; ++r) y[r] = mfma(a[r], c2[rt][r], y[r]);
       }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[r] = an[r];
     }
     const d4 ys = (y[0] + y[1]) + (y[2] + y[3]);
 #pragma unroll
@@ -400,12 +412,18 @@ __device__ inline void update_group(const Lds &L, int kind, int s, int q0, int n
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) b[kk] = -yw[(q * 16 + 4 * kk + (ln >> 4)) * 16 + (ln & 15)];
     const ldbl *vp = L.vc + (g * 16 + (ln >> 4)) * LDVC + rbase + (ln & 15);
+    // A operands two MFMAs ahead (a ring of two), for the same reason
+    double a0 = vp[0], a1 = vp[16];
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
-        if (rt >= rt0 && rbase + rt * 16 < vrows)
-          c2[rt] = mfma(vp[4 * kk * LDVC + rt * 16], b[kk], c2[rt]);
+        const int nx = kk * RT + rt + 2;  // the operand two steps ahead
+        const double an = nx < 4 * RT ? (double)vp[4 * (nx / RT) * LDVC + (nx % RT) * 16] : 0.0;
+        __builtin_amdgcn_sched_barrier(0);  // keep the load ahead of the MFMA
+        if (rt >= rt0 && rbase + rt * 16 < vrows) c2[rt] = mfma(a0, b[kk], c2[rt]);
+        a0 = a1;
+        a1 = an;
       }
     }
   }

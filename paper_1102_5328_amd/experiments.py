@@ -511,6 +511,8 @@ def _training_rows(db):
     for r in db.values():
         if r.get("kind", "normal") not in ("normal", "batched") or r["gflops"] <= 0:
             continue
+        if r.get("p", 1) > 1 or r.get("units", 0):  # the model's regime: flat tree, whole device
+            continue
         X.append(features(r["M"], r["N"], r["nb"], r["ib"], r.get("batch", 1)))
         y.append(math.log(r["gflops"]))
     return np.array(X, dtype=np.float64), np.array(y, dtype=np.float64)
@@ -566,6 +568,10 @@ def train_ensemble(X, y, nmodels=5, epochs=300, batch=64, lr=1e-3, seed=0):
 
 
 TRAIN_SHAPES = dict(count=420, seed=11, lo=256, hi=16384)
+# Candidates of the cost model: the tile orders up to 256 with IB of 16, 32
+# or 64 dividing them (every size's best pair in the square sweep is among
+# them; the larger tiles and IBs trail at every size).
+MLP_PAIRS = [(nb, ib) for nb in (64, 96, 128, 192, 256) for ib in (16, 32, 64) if nb % ib == 0]
 TEST_SHAPES = dict(count=200, seed=5)
 
 
@@ -582,7 +588,7 @@ def collect(db, which, budget_s, reps=2):
     'normal') or on the held-out shapes (kind 'heldout': never used for
     training) until done or `budget_s` seconds have passed; resumable, the
     database keeps what was measured. Returns True when complete."""
-    pairs = R.config2_pairs()
+    pairs = MLP_PAIRS
     meas = R.Measurer(db, reps=reps)
     train, test = _shape_sets()
     shapes, kind = (train, "normal") if which == "train" else (test, "heldout")
@@ -605,7 +611,7 @@ def collect(db, which, budget_s, reps=2):
 def heldout_es(db):
     """{(M, N): {pair: median GFLOP/s}} of the exhaustive search on the
     held-out shapes (every pair must have been measured)."""
-    pairs = R.config2_pairs()
+    pairs = MLP_PAIRS
     _, test_shapes = _shape_sets()
     return {(M, N): {p: db[R.Measurer.key("heldout", M, N, p[0], p[1])]["gflops"] for p in pairs}
             for (M, N) in test_shapes}
@@ -629,7 +635,7 @@ def ensemble_predict(model, M, N, batch=1, pairs=None):
     import paper_1102_5328_amd as tq
     from . import _lib
     params, fmean, fstd, ymean, ystd = model
-    pairs = pairs or R.config2_pairs()
+    pairs = pairs or MLP_PAIRS
     X = np.array([features(M, N, nb, ib, batch) for nb, ib in pairs])
     Xs = torch.from_numpy(((X - fmean) / fstd).astype(np.float32)).cuda()
     P = torch.from_numpy(np.ascontiguousarray(params, dtype=np.float32)).cuda()
@@ -649,16 +655,23 @@ def evaluate(es, model, table=None, ps=None):
     the other reading of the spread, (max - min) / mean of the predicted
     GFLOP/s at the chosen pair, would have fallen back."""
     import paper_1102_5328_amd as tq
-    pairs = R.config2_pairs()
+    pairs = MLP_PAIRS
     cand = np.array(pairs, dtype=np.int32).reshape(-1)
     params, fmean, fstd, ymean, ystd = model
     table = table or os.path.join(TUNING, "decision_table.txt")
     tq.tune_load(table if os.path.exists(table) else os.devnull)
-    ps = ps or shipped_preselection()
+    ps = [p for p in (ps or shipped_preselection()) if p in pairs] or pairs
     rows = []
     t_choose = 0.0
+    skipped = 0
     try:
         for (M, N), rates in es.items():
+            # the model and the timings are of the flat tree: shapes whose
+            # table entry is a tree (tall shapes) are answered by the table
+            # alone and are not scored here
+            if tq.tune_domains(M, N, 1) > 1:
+                skipped += 1
+                continue
             tq.check(_lib_set_model(None, 0, fmean, fstd, ymean, ystd, cand), "model off")
             tnb, tib, _ = tq.tune(M, N, 1)
             tq.check(_lib_set_model(params, len(params), fmean, fstd, ymean, ystd, cand), "model on")
@@ -688,7 +701,8 @@ def evaluate(es, model, table=None, ps=None):
     reg_m = np.array([1.0 - r["model_gflops"] / r["best_gflops"] for r in rows])
     fl = np.array([tq.flops(r["M"], r["N"]) for r in rows])
     return {
-        "n_test": len(rows), "fallback_rate": float(np.mean([r["fallback"] for r in rows])),
+        "n_test": len(rows), "n_tree_shapes_skipped": skipped,
+        "fallback_rate": float(np.mean([r["fallback"] for r in rows])),
         "fallback_rate_range_reading": float(np.mean([r["spread_range"] > 0.05 for r in rows])),
         "preselected_fallback_pairs": [list(p) for p in ps],
         "regret_mean": float(reg.mean()), "regret_max": float(reg.max()),
@@ -715,7 +729,7 @@ def mlp(out_dir, db):
     log("training rows: %d" % len(y))
     params, fmean, fstd, ymean, ystd, losses, t_train = train_ensemble(X, y)
     rep = {"train_rows": int(len(y)), "train_seconds": t_train, "final_losses": losses,
-           "pairs": [list(p) for p in R.config2_pairs()]}
+           "pairs": [list(p) for p in MLP_PAIRS]}
     rep.update(evaluate(es, (params, fmean, fstd, ymean, ystd)))
     log("mlp: regret mean %.4f max %.4f (model only %.4f, table only %.4f), fallback %.2f" %
         (rep["regret_mean"], rep["regret_max"], rep["regret_model_only_mean"],
@@ -725,7 +739,7 @@ def mlp(out_dir, db):
     with open(os.path.join(out_dir, "mlp_model.json"), "w") as f:
         json.dump({"params": params.tolist(), "fmean": fmean.tolist(), "fstd": fstd.tolist(),
                    "ymean": ymean, "ystd": ystd,
-                   "cand": np.array(R.config2_pairs()).reshape(-1).tolist()}, f)
+                   "cand": np.array(MLP_PAIRS).reshape(-1).tolist()}, f)
     return rep
 
 

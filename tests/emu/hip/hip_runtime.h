@@ -66,6 +66,7 @@ inline void __builtin_amdgcn_s_sleep(int) { std::this_thread::yield(); }
 #define __builtin_amdgcn_fence(...) std::atomic_thread_fence(std::memory_order_seq_cst)
 #define __builtin_amdgcn_s_waitcnt(x) std::atomic_thread_fence(std::memory_order_seq_cst)
 #define __builtin_amdgcn_s_setprio(x) ((void)0)
+#define __builtin_amdgcn_sched_barrier(x) ((void)0)
 inline void __builtin_amdgcn_wave_barrier() { g_wave_bar[threadIdx.x >> 6]->arrive_and_wait(); }
 inline double __shfl(double v, int src, int width = 64) {
   int w = threadIdx.x >> 6, l = threadIdx.x & 63;

@@ -3,8 +3,12 @@ ensemble trained on the GPU by the library's kernels on the recorded tuner
 timings chooses (NB, IB) for the 200 held-out shapes (M, N log-uniform in
 [256, 32768], seed 5); its regret against the exhaustive search (recorded
 timings of every pair on every held-out shape) is compared with that of the
-decision table alone. No factorization is timed here: the choices are
-scored with the recorded exhaustive-search timings."""
+decision table alone. The candidates are the model's 14 pairs (tile orders
+up to 256, IB of 16, 32 or 64), the exhaustive search is over them, and the
+timings were taken with the shipped library on the whole device with the
+flat tree; held-out shapes that the table answers with a tree are left out.
+No factorization is timed here: the choices are scored with the recorded
+exhaustive-search timings."""
 import os
 
 import pytest
@@ -28,7 +32,9 @@ def test_model_regret_against_exhaustive_search():
     params, fmean, fstd, ymean, ystd, losses, _ = E.train_ensemble(X, y)
     rep = E.evaluate(es, (params, fmean, fstd, ymean, ystd))
     print({k: v for k, v in rep.items() if k != "rows"})
-    assert rep["n_test"] == 200
+    # every held-out shape but the tall ones the table answers with a tree
+    assert rep["n_test"] + rep["n_tree_shapes_skipped"] == 200
+    assert rep["n_test"] >= 150
     # The target: within 3 % of the exhaustive best on average, with the
     # pruned search as the fallback when the ensemble disagrees.
     assert rep["regret_mean"] <= 0.03
