@@ -63,11 +63,13 @@ class Measurer:
                 self.db = json.load(f)
         self._shape = None
         self._A0 = None
+        self._unsaved = 0  # new measurements since the last save
         # (units, torch stream): runs with that unit count go to a stream
         # restricted to those compute units (a caller's masked stream)
         self.masked = None
 
     def save(self):
+        self._unsaved = 0
         if self.db_path:
             tmp = self.db_path + ".tmp"
             with open(tmp, "w") as f:
@@ -149,6 +151,9 @@ class Measurer:
             print("measured %s %dx%d nb=%d ib=%d units=%d p=%d: %.1f GFLOP/s (%.2f s)"
                   % (kind, M, N, nb, ib, units, p, med, sec), flush=True)
         del A, T
+        self._unsaved += 1
+        if self._unsaved >= 20:  # a run cut short keeps what it measured
+            self.save()
         return med, sec
 
 
