@@ -2,7 +2,8 @@
 emulation in tests/emu (every lane a host thread, LDS laid out as on the
 device, MFMA with the measured gfx950 lane layout) with AddressSanitizer:
 the index arithmetic of every task kind stays in bounds, and the results
-match the oracle. Covers every row-wave class (NB <= 128: one wave per
+match the oracle: R after sign normalisation, Q^T A = R, and Q (Q^T A) = A
+(the reverse application). Covers every row-wave class (NB <= 128: one wave per
 128-row slab of a column group; NB <= 256: two; NB <= 512: four), ragged
 tiles, inner blocks that do not divide NB, the communication-avoiding tree, inner blocks wider than a
 register panel (the T assembly across panels), the batched union DAG and
