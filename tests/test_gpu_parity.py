@@ -89,3 +89,18 @@ def test_ill_conditioned_invariants():
     A = inputs.ill_conditioned(256, seed=0)
     r = check_factorization(A, 64, 16, cond=1e12)
     _assert_ok(r)
+
+
+@pytest.mark.parametrize("M,N,nb,ib", [(300, 200, 64, 16), (384, 320, 128, 16)])
+def test_power_of_two_scaling_is_exact(M, N, nb, ib):
+    """The kernels form each reflector from the unscaled norm of its column
+    (the range stated in tileqr.h). For s = 2^(+-400), about 1e(+-120), every
+    operation scales exactly, so R(sA) = s R(A) and the reflectors are
+    unchanged, bit for bit."""
+    A = inputs.normal(M, N, seed=23)
+    VR, _, _ = factor_gpu(A, nb, ib, units=16)
+    for e in (400, -400):
+        s = 2.0 ** e
+        VRs, _, _ = factor_gpu(A * s, nb, ib, units=16)
+        np.testing.assert_array_equal(oracle.upper(VRs), oracle.upper(VR) * s)
+        np.testing.assert_array_equal(np.tril(VRs, -1), np.tril(VR, -1))

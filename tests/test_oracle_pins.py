@@ -312,3 +312,20 @@ def test_lstsq_matches_lapack_and_normal_equations(orc, shape):
     assert np.linalg.norm(A.T @ (A @ X - B)) <= 1e-10 * np.linalg.norm(A) ** 2 * np.linalg.norm(X)
     res = np.linalg.norm(A @ X - B, axis=0)
     assert np.allclose(np.linalg.norm(QtB[shape[1]:], axis=0), res, rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("e", [400, -400])
+def test_power_of_two_scaling_is_exact(orc, e):
+    """QR(sA) = Q (sR) with the same reflectors. For s = 2^e every operation
+    of the unscaled-norm reflector (Section 2.1 reading) scales exactly while
+    no square leaves the normal range, so R is scaled bit for bit and V and
+    tau are unchanged: the supported range of 1e-150 .. 1e150 holds exactly
+    at 2^(+-400), about 1e(+-120). A stray additive constant or a rescaling
+    that depends on the magnitude would break it."""
+    A = inputs.normal(60, 40, seed=17)
+    s = 2.0 ** e
+    VR, tau = orc.geqr2(A)
+    VRs, taus = orc.geqr2(A * s)
+    np.testing.assert_array_equal(orc.upper(VRs), orc.upper(VR) * s)
+    np.testing.assert_array_equal(np.tril(VRs, -1), np.tril(VR, -1))
+    np.testing.assert_array_equal(taus, tau)
