@@ -169,6 +169,10 @@ def main():
     kern_ms = sum(e0.elapsed_time(e1) for e0, e1 in evs) / args.steps
     units = tq.tune_units(N, N, 1)
     traffic = measured_traffic(N, nb, ib, units)
+    # The ceiling of the FP64 matrix instruction itself at the kernel's
+    # occupancy (two workgroups of four waves per CU), measured live by a
+    # register-only probe, next to the published peak.
+    ceil_tf, ceil_ghz = tq.mfma_probe(2, 50000)
     ms_per_step = dt * 1e3 / args.steps
     flops = tq.flops(N, N)
     value = flops / (ms_per_step * 1e-3) / 1e9
@@ -206,7 +210,10 @@ def main():
                      "kernel": "tq_persistent (whole DAG, one launch)",
                      "kernel_ms": round(kern_ms, 3),
                      "hbm_GBps": (round(traffic / (kern_ms * 1e-3) / 1e9, 1)
-                                  if traffic else None)},
+                                  if traffic else None),
+                     "mfma_probe_TFLOPs": round(ceil_tf, 2),
+                     "frac_of_mfma_probe": round(achieved / ceil_tf, 4) if ceil_tf > 0 else None,
+                     "probe_shader_GHz": round(ceil_ghz, 2)},
     }
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(A0, args.cpu_seconds)

@@ -244,6 +244,18 @@ int qr_ssrfb_bench(int NB, int IB, int calls, int workers, double *seconds);
 int qr_ssrfb_bench_flush(int NB, int IB, int calls, int workers, int64_t flush_bytes,
                          double *seconds);
 
+/* Measurement support (not an operation of the paper): the sustained rate
+ * of v_mfma_f64_16x16x4f64, the FP64 matrix instruction of the DLARFB and
+ * DSSRFB kernels, with register operands and eight independent accumulator
+ * chains per wave, so that no memory access, barrier or dependence stall
+ * limits it. wg_per_cu (1..8) workgroups of four waves run on every compute
+ * unit, `iters` rounds of the eight products each. *tflops (host) receives
+ * the whole chip's FP64 rate; *ghz (host, may be NULL) the shader clock the
+ * probe measured over its own run. It is the ceiling that Step 1's rates
+ * (Section 5) and the factorization's are read against, next to the published
+ * peak. Errors: -1 wg_per_cu, -2 iters, -3 tflops null. */
+int qr_mfma_probe(int wg_per_cu, int iters, double *tflops, double *ghz);
+
 /* ---------------------------------------------------------------------- */
 /* Tuning decision (Problem 2.1: instantaneous choice of (NB, IB))          */
 /* ---------------------------------------------------------------------- */

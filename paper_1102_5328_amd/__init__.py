@@ -273,6 +273,15 @@ def ssrfb_bench_flush(nb, ib, calls=50, workers=0, flush_bytes=1 << 30):
     return sec.value
 
 
+def mfma_probe(wg_per_cu=2, iters=50000):
+    """qr_mfma_probe: the sustained FP64 MFMA rate of the chip (TFLOP/s) and
+    the shader clock (GHz) measured over the probe's run."""
+    tf, ghz = ctypes.c_double(), ctypes.c_double()
+    check(_lib.lib().qr_mfma_probe(wg_per_cu, iters, ctypes.byref(tf), ctypes.byref(ghz)),
+          "qr_mfma_probe")
+    return tf.value, ghz.value
+
+
 def flops(M, N):
     return _lib.lib().qr_flops(M, N)
 

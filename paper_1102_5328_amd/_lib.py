@@ -46,6 +46,7 @@ SIGNATURES = {
     "qr_tile_task": (c_int, [c_int, c_vp, c_i64, c_i64, c_i64, c_int, c_int, c_vp, c_int, c_int, c_int, c_vp]),
     "qr_ssrfb_bench": (c_int, [c_int, c_int, c_int, c_int, c_dblp]),
     "qr_ssrfb_bench_flush": (c_int, [c_int, c_int, c_int, c_int, c_i64, c_dblp]),
+    "qr_mfma_probe": (c_int, [c_int, c_int, c_dblp, c_dblp]),
     "qr_tune": (c_int, [c_i64, c_i64, c_i64, c_intp, c_intp, c_intp]),
     "qr_tune_load": (c_int, [ctypes.c_char_p]),
     "qr_tune_units": (c_int, [c_i64, c_i64, c_i64, c_intp]),

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtileqr.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["tileqr_device.hip", "tileqr_mlp.hip", "tileqr_api.cpp", "plan.cpp"]
+SOURCES = ["tileqr_device.hip", "tileqr_mlp.hip", "tileqr_probe.hip", "tileqr_api.cpp", "plan.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", "-Wno-unused-value"]

@@ -52,3 +52,9 @@ int *tq_noalloc_scratch_if_set(int dev);
 // program-order DAG of one matrix (tasks decoded from the ticket).
 hipError_t tq_launch_noalloc(int *scratch_ptr, const MatDesc &md, int64_t ntasks, int64_t nctr,
                              int grid, size_t lds, long long timeout, hipStream_t st);
+// FP64 MFMA rate probe: `grid` workgroups of four waves, each wave `iters`
+// rounds of tq_mfma_probe_chains() independent v_mfma_f64_16x16x4f64 chains.
+// out holds 2 + 256 * grid doubles: [0] shader-clock ticks and [1] wall-clock
+// ticks of workgroup 0, then one checksum per lane.
+int tq_mfma_probe_chains();
+hipError_t tq_launch_mfma_probe(double *out, int grid, int iters, hipStream_t st);

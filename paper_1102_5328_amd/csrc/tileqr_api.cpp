@@ -941,6 +941,47 @@ int qr_ssrfb_bench_flush(int NB, int IB, int calls, int workers, int64_t flush_b
   return rc;
 }
 
+// The FP64 MFMA ceiling: wg_per_cu workgroups of four waves per compute unit
+// run the register-only probe; rate from the launch time, clock from the
+// probe's own shader-clock and wall-clock spans.
+int qr_mfma_probe(int wg_per_cu, int iters, double *tflops, double *ghz) {
+  if (wg_per_cu < 1 || wg_per_cu > 8) return -1;
+  if (iters < 1) return -2;
+  if (!tflops) return -3;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DevState *ds;
+  int rc = dev_state(&ds);
+  if (rc) return rc;
+  const int grid = wg_per_cu * ds->ncu;
+  double *out = nullptr;
+  if (hipMalloc(&out, sizeof(double) * (2 + (int64_t)grid * 256)) != hipSuccess)
+    return TILEQR_ERR_NOMEM;
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  // a short launch first, so the timed one starts at the running clock
+  hipError_t he = tq_launch_mfma_probe(out, grid, iters / 8 + 1, 0);
+  hipEventRecord(e0, 0);
+  if (he == hipSuccess) he = tq_launch_mfma_probe(out, grid, iters, 0);
+  hipEventRecord(e1, 0);
+  if (hipEventSynchronize(e1) != hipSuccess || he != hipSuccess) rc = TILEQR_ERR_HIP;
+  float ms = 0;
+  hipEventElapsedTime(&ms, e0, e1);
+  double span[2] = {0.0, 0.0};
+  if (!rc && hipMemcpy(span, out, sizeof(span), hipMemcpyDeviceToHost) != hipSuccess)
+    rc = TILEQR_ERR_HIP;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipFree(out);
+  if (rc) return rc;
+  const double flops = 2048.0 * tq_mfma_probe_chains() * (double)iters * 4.0 * grid;
+  *tflops = ms > 0 ? flops / (ms * 1e-3) / 1e12 : 0.0;
+  if (ghz)
+    *ghz = (span[1] > 0 && ds->wall_khz > 0) ? span[0] / (span[1] / (ds->wall_khz * 1e3)) / 1e9
+                                             : 0.0;
+  return 0;
+}
+
 // ------------------------------------------------------------------ tuning
 
 int qr_tune_load(const char *path) {

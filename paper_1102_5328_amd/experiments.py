@@ -758,12 +758,38 @@ def _lib_set_model(params, nmodels, fmean, fstd, ymean, ystd, cand):
                                         c.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(c) // 2)
 
 
+def mfma_ceiling(out_dir):
+    """The FP64 MFMA probe at 1..4 waves per SIMD, next to the Step-1 DSSRFB
+    rate (128/16) at one and two workgroups per compute unit: how close the
+    update kernel runs to what the matrix instruction itself sustains."""
+    import torch
+    import paper_1102_5328_amd as tq
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    rows = []
+    for w in (1, 2, 3, 4):
+        tf, ghz = tq.mfma_probe(w, 50000)
+        rows.append({"waves_per_simd": w, "probe_TFLOPs": tf, "shader_GHz": ghz})
+        log("probe: %d wave(s)/SIMD %.2f TFLOP/s at %.2f GHz (%.1f %% of 78.6)" %
+            (w, tf, ghz, 100.0 * tf / 78.6))
+    step1 = []
+    for wpc in (1, 2):
+        calls = 50
+        sec = tq.ssrfb_bench(128, 16, calls, wpc * ncu)
+        tf = 4.0 * 128 ** 3 * calls * wpc * ncu / sec / 1e12
+        ref = rows[wpc - 1]["probe_TFLOPs"]
+        step1.append({"workgroups_per_cu": wpc, "TFLOPs": tf, "frac_of_probe": tf / ref})
+        log("Step 1 DSSRFB 128/16: %d workgroup(s)/CU %.2f TFLOP/s = %.3f of the probe" %
+            (wpc, tf, tf / ref))
+    with open(os.path.join(out_dir, "mfma_ceiling_report.json"), "w") as f:
+        json.dump({"probe": rows, "step1_128_16": step1}, f, indent=1)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("what", choices=["batched", "batched-tune", "sweep", "tune", "step1-cold",
                                      "cu-scaling", "tune-units", "tune-budgets", "ship",
                                      "collect-train",
-                                     "collect-heldout", "mlp"])
+                                     "collect-heldout", "mlp", "mfma-ceiling"])
     ap.add_argument("--out", required=True)
     ap.add_argument("--db", default=None, help="JSON measurement database (read and extended)")
     ap.add_argument("--budget", type=float, default=600.0, help="seconds of measuring (collect)")
@@ -794,6 +820,8 @@ def main(argv=None):
         tune_units(a.out, db, tuple(int(x) for x in a.units.split(",")))
     elif a.what == "tune-budgets":
         tune_budgets(a.out, db)
+    elif a.what == "mfma-ceiling":
+        mfma_ceiling(a.out)
     elif a.what in ("collect-train", "collect-heldout"):
         done = collect(db, a.what.split("-")[1], a.budget)
         log("collect %s: %s" % (a.what, "complete" if done else "budget reached"))

@@ -24,3 +24,18 @@ def test_step1_warm_and_flushed(nb, ib):
     g_cold = flops * ncu / cold / 1e9
     print(nb, ib, "warm %.0f GFLOP/s, flushed %.0f GFLOP/s" % (g_warm, g_cold))
     assert g_warm > 100.0 and g_cold > 10.0
+
+
+def test_mfma_probe_rate_and_clock():
+    """The FP64 MFMA probe: a finite, positive rate no higher than the
+    published peak (78.6 TFLOP/s dense FP64), more waves per SIMD never much
+    slower than one, and a shader clock within the chip's range."""
+    import paper_1102_5328_amd as tq
+    one, ghz1 = tq.mfma_probe(1, 20000)
+    two, ghz2 = tq.mfma_probe(2, 20000)
+    print("MFMA probe: 1 wave/SIMD %.2f TFLOP/s at %.2f GHz, 2 waves/SIMD %.2f TFLOP/s at %.2f GHz"
+          % (one, ghz1, two, ghz2))
+    for tf, ghz in ((one, ghz1), (two, ghz2)):
+        assert math.isfinite(tf) and 1.0 < tf <= 78.6 * 1.02
+        assert 0.5 < ghz < 3.0
+    assert two > 0.9 * one

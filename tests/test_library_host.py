@@ -208,6 +208,11 @@ def test_other_argument_errors(lib):
     assert f(64, 16, 1, -1, 0, ctypes.byref(sec)) == -4
     assert f(64, 16, 1, 0, -8, ctypes.byref(sec)) == -5
     assert f(64, 16, 1, 0, 0, None) == -6
+    tf = ctypes.c_double()
+    assert lib.qr_mfma_probe(0, 10, ctypes.byref(tf), None) == -1
+    assert lib.qr_mfma_probe(9, 10, ctypes.byref(tf), None) == -1
+    assert lib.qr_mfma_probe(2, 0, ctypes.byref(tf), None) == -2
+    assert lib.qr_mfma_probe(2, 10, None, None) == -3
     assert lib.qr_T_size(-1, 4, 64, 16) == -1
     assert lib.qr_T_size(4, -1, 64, 16) == -2
     assert lib.qr_T_size(4, 4, 0, 16) == -3
