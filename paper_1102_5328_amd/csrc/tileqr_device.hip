@@ -660,14 +660,14 @@ __device__ __forceinline__ void apply_strip_fast(const Lds &L, const double *V, 
   }
   double pv[VPL], pt[IB * IB / NTHR > 0 ? IB * IB / NTHR : 1], pc[IB / 4];
   constexpr int TPL = IB * IB / NTHR > 0 ? IB * IB / NTHR : 1;
+  // The prefetch registers hold the values as loaded: the unit-lower and
+  // triangle selections are applied when the block is staged, so that no
+  // instruction right after the loads waits for them (a select there would
+  // make the prefetch synchronous).
   auto load_v = [&](int s) {
     const gdbl *Vb = gp(V) + (int64_t)(s + vc) * ldv + vr;
 #pragma unroll
-    for (int u = 0; u < VPL; ++u) {
-      const int gc = s + vc + 2 * u;
-      const double val = Vb[(int64_t)(2 * u) * ldv];
-      pv[u] = (kind == VK_UNIT) ? (vr < gc ? 0.0 : (vr == gc ? 1.0 : val)) : val;
-    }
+    for (int u = 0; u < VPL; ++u) pv[u] = Vb[(int64_t)(2 * u) * ldv];
   };
   auto load_t = [&](int s) {
     const gdbl *Tb = gp(T) + (int64_t)s * ldt;
@@ -675,8 +675,7 @@ __device__ __forceinline__ void apply_strip_fast(const Lds &L, const double *V, 
     for (int u = 0; u < TPL; ++u) {
       const int e = u * NTHR + tid;
       const int a = e / IB, c = e % IB;
-      const double val = Tb[min(a, IB - 1) + (int64_t)c * ldt];
-      pt[u] = (e < IB * IB && a <= c) ? val : 0.0;
+      pt[u] = Tb[min(a, IB - 1) + (int64_t)c * ldt];
     }
   };
   auto load_c1 = [&](int s) {
@@ -692,11 +691,16 @@ __device__ __forceinline__ void apply_strip_fast(const Lds &L, const double *V, 
     {
       ldbl *lb = L.vc + vc * LDVC + vr;
 #pragma unroll
-      for (int u = 0; u < VPL; ++u) lb[2 * u * LDVC] = pv[u];
+      for (int u = 0; u < VPL; ++u) {
+        const int gc = s + vc + 2 * u;
+        const double v = pv[u];
+        lb[2 * u * LDVC] = (kind == VK_UNIT) ? (vr < gc ? 0.0 : (vr == gc ? 1.0 : v)) : v;
+      }
 #pragma unroll
       for (int u = 0; u < TPL; ++u) {
         const int e = u * NTHR + tid;
-        if (e < IB * IB) L.ts[(e / IB) * LDTS + (e % IB)] = pt[u];
+        const int a = e / IB, c = e % IB;
+        if (e < IB * IB) L.ts[a * LDTS + c] = a <= c ? pt[u] : 0.0;
       }
     }
     const int sn = s + IB;
