@@ -160,11 +160,13 @@ __device__ inline Lds make_lds(double *lds_base, const MatDesc &m) {
 // V chunks [gc0, gc0 + 16*ng) (columns of V, rows 0 .. 128*RW) into per-lane
 // registers: element e = ebase + u*256 + tid sits at column e / ROWS, row
 // e % ROWS, so a lane walks one row (or two, ROWS = 512) and steps over
-// columns with a fixed stride; zero outside the reflector support. VK_UNIT:
-// column gc has an implicit 1 at row gc and 0 above.
+// columns with a fixed stride. The registers hold the values as loaded (every
+// read inside the block, at clamped indices); vstage_store applies the
+// reflector support and the unit diagonal. Selecting here would make each
+// load wait at once, and with it every load issued before it.
 template <int RW>
 __device__ inline void vstage_load(double (&v)[PF], const double *V, int64_t ldv, int vrows,
-                                   int kind, int gc0, int kvalid, int ebase, int total) {
+                                   int gc0, int kvalid, int ebase, int total) {
   constexpr int ROWS = Geo<RW>::ROWS;
   constexpr int CPU = ROWS <= NTHR ? NTHR / ROWS : 1;  // columns per step of u (ROWS <= 256)
   const int tid = tid_x();
@@ -181,9 +183,7 @@ __device__ inline void vstage_load(double (&v)[PF], const double *V, int64_t ldv
       if (ebase + u * NTHR >= total) break;
       const int du = ROWS <= NTHR ? u * CPU : u >> 1;
       const int dr = ROWS <= NTHR ? 0 : (u & 1) * NTHR;
-      const double val = Vb[(int64_t)du * ldv + dr];
-      const int r = r0 + dr, gc = c0 + du;
-      v[u] = (kind == VK_UNIT) ? (r < gc ? 0.0 : (r == gc ? 1.0 : val)) : val;
+      v[u] = Vb[(int64_t)du * ldv + dr];
     }
     return;
   }
@@ -192,36 +192,39 @@ __device__ inline void vstage_load(double (&v)[PF], const double *V, int64_t ldv
     // ROWS = 512: u even -> rows r0, u odd -> rows r0 + 256 of the same column
     const int du = ROWS <= NTHR ? u * CPU : u >> 1;
     const int dr = ROWS <= NTHR ? 0 : (u & 1) * NTHR;
-    const int e = e0 + u * NTHR;
     const int r = r0 + dr, gc = c0 + du;
-    // always read an element of the block (clamped indices), then select:
-    // no branch per element
-    const double val = Vg[min(r, vrows - 1) + (int64_t)min(gc, kvalid - 1) * ldv];
-    const bool ok = e < total && r < vrows && gc < kvalid;
-    const double y = (kind == VK_UNIT) ? (r < gc ? 0.0 : (r == gc ? 1.0 : val)) : val;
-    v[u] = ok ? y : 0.0;
+    // always read an element of the block (clamped indices): no branch per element
+    v[u] = Vg[min(r, vrows - 1) + (int64_t)min(gc, kvalid - 1) * ldv];
   }
 }
 
-// Registers of vstage_load into the LDS chunks (chunk-relative column c at
-// c * ldvc), rows up to vrows rounded to 16 (the zero padding of the last
-// row tile).
+// Registers of vstage_load (same block: vrows, gc0, kvalid, ebase, total)
+// into the LDS chunks (chunk-relative column c at c * ldvc), rows up to vrows
+// rounded to 16 (the zero padding of the last row tile): zero outside the
+// reflector support; VK_UNIT: column gc has an implicit 1 at row gc and 0
+// above.
 template <int RW>
-__device__ inline void vstage_store(const Lds &L, const double (&v)[PF], int vrows, int ebase,
-                                    int total) {
+__device__ inline void vstage_store(const Lds &L, const double (&v)[PF], int vrows, int kind,
+                                    int gc0, int kvalid, int ebase, int total) {
   constexpr int ROWS = Geo<RW>::ROWS, LDVC = Geo<RW>::LDVC;
   constexpr int CPU = ROWS <= NTHR ? NTHR / ROWS : 1;
   const int rlim = (vrows + 15) & ~15;
   const int e0 = ebase + tid_x();
   const int r0 = e0 % ROWS, c0 = e0 / ROWS;
   ldbl *lb = L.vc + c0 * LDVC + r0;
+  auto value = [&](int u, int du, int dr) {
+    const int r = r0 + dr, gc = gc0 + c0 + du;
+    const bool ok = e0 + u * NTHR < total && r < vrows && gc < kvalid;
+    const double y = (kind == VK_UNIT) ? (r < gc ? 0.0 : (r == gc ? 1.0 : v[u])) : v[u];
+    return ok ? y : 0.0;
+  };
   if (rlim == ROWS) {  // uniform: every row stored; e < total is uniform per u
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
       if (ebase + u * NTHR >= total) break;
       const int du = ROWS <= NTHR ? u * CPU : u >> 1;
       const int dr = ROWS <= NTHR ? 0 : (u & 1) * NTHR;
-      lb[du * LDVC + dr] = v[u];
+      lb[du * LDVC + dr] = value(u, du, dr);
     }
     return;
   }
@@ -229,7 +232,7 @@ __device__ inline void vstage_store(const Lds &L, const double (&v)[PF], int vro
   for (int u = 0; u < PF; ++u) {
     const int du = ROWS <= NTHR ? u * CPU : u >> 1;
     const int dr = ROWS <= NTHR ? 0 : (u & 1) * NTHR;
-    if (e0 + u * NTHR < total && r0 + dr < rlim) lb[du * LDVC + dr] = v[u];
+    if (e0 + u * NTHR < total && r0 + dr < rlim) lb[du * LDVC + dr] = value(u, du, dr);
   }
 }
 
@@ -240,14 +243,15 @@ __device__ inline void stage_v(const Lds &L, const double *V, int64_t ldv, int v
   const int total = ng * 16 * Geo<RW>::ROWS;
   for (int base = 0; base < total; base += PF * NTHR) {
     double v[PF];
-    vstage_load<RW>(v, V, ldv, vrows, kind, gc0, kvalid, base, total);
-    vstage_store<RW>(L, v, vrows, base, total);
+    vstage_load<RW>(v, V, ldv, vrows, gc0, kvalid, base, total);
+    vstage_store<RW>(L, v, vrows, kind, gc0, kvalid, base, total);
   }
 }
 
 // T_s (ibw x ibw upper triangle of the block at Tb, leading dimension ldt)
 // as ibp x ibp with zeros elsewhere (ibp <= TQ_TS_MAX); element
-// e = u*256 + tid at (a = e / TQ_TS_MAX, c = e % TQ_TS_MAX).
+// e = u*256 + tid at (a = e / TQ_TS_MAX, c = e % TQ_TS_MAX). Loaded as is
+// (clamped indices); tstage_store keeps the triangle.
 constexpr int TPF = TQ_TS_MAX * TQ_TS_MAX / NTHR;
 __device__ inline void tstage_load(double (&v)[TPF], const double *Tb, int64_t ldt, int ibw) {
   const gdbl *Tg = gp(Tb);
@@ -255,22 +259,23 @@ __device__ inline void tstage_load(double (&v)[TPF], const double *Tb, int64_t l
   for (int u = 0; u < TPF; ++u) {
     const int e = u * NTHR + tid_x();
     const int a = e / TQ_TS_MAX, c = e % TQ_TS_MAX;
-    const double val = Tg[min(a, ibw - 1) + (int64_t)min(c, ibw - 1) * ldt];
-    v[u] = (a <= c && c < ibw) ? val : 0.0;
+    v[u] = Tg[min(a, ibw - 1) + (int64_t)min(c, ibw - 1) * ldt];
   }
 }
-__device__ inline void tstage_store(const Lds &L, const double (&v)[TPF], int ibp) {
+__device__ inline void tstage_store(const Lds &L, const double (&v)[TPF], int ibp, int ibw) {
   const int ldts = ibp + 1;
 #pragma unroll
   for (int u = 0; u < TPF; ++u) {
     const int e = u * NTHR + tid_x();
     const int a = e / TQ_TS_MAX, c = e % TQ_TS_MAX;
-    if (a < ibp && c < ibp) L.ts[a * ldts + c] = v[u];
+    if (a < ibp && c < ibp) L.ts[a * ldts + c] = (a <= c && c < ibw) ? v[u] : 0.0;
   }
 }
 
 // C1 rows [s, s + ibw) of the wave's 16 columns (column group cg), element
-// e = u*64 + lane at (a = e / 16, c = e % 16); ibw <= 32.
+// e = u*64 + lane at (a = e / 16, c = e % 16); ibw <= 32. Loaded as is
+// (clamped indices): rows a >= ibw and columns c >= ncols hold copies of
+// valid elements, which the users mask.
 constexpr int CPF = TQ_TS_MAX * 16 / 64;
 __device__ inline void c1_load(double (&v)[CPF], const double *C1, int64_t ldc1, int s, int ibw,
                                int ncols, int cg) {
@@ -280,8 +285,7 @@ __device__ inline void c1_load(double (&v)[CPF], const double *C1, int64_t ldc1,
 #pragma unroll
   for (int u = 0; u < CPF; ++u) {
     const int a = 4 * u + (ln >> 4);
-    const double val = Cb[min(a, ibw - 1)];
-    v[u] = (a < ibw && c < ncols) ? val : 0.0;
+    v[u] = Cb[min(a, ibw - 1)];
   }
 }
 
@@ -517,14 +521,40 @@ __device__ __forceinline__ void apply_strip(const Lds &L, const double *V, int64
   const bool pf = tl && nqb <= L.gmax && nqb * 16 * ROWS <= PF * NTHR && !notrans;
   ldbl *yw = L.y + cg * L.ibp * 16;
   const bool c1w = C1 != nullptr && rb == 0 && gact;
+  // C2 as loaded (clamped rows of a valid column), then the first block's
+  // prefetch, then the masks: the masks wait for the C2 loads only
   d4 c2[RT];
-  load_c2(c2, C2, ldc2, vrows, min(col, ncols - 1), colok && gact, rbase);
+  {
+    const int g = ln >> 4;
+    const gdbl *Cc = gp(C2) + (int64_t)min(col, ncols - 1) * ldc2;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const int lo = rbase + rt * 16;  // uniform
+      if (lo < vrows) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) c2[rt][r] = Cc[min(lo + 4 * r + g, vrows - 1)];
+      } else {
+        c2[rt] = d4{0.0, 0.0, 0.0, 0.0};
+      }
+    }
+  }
   double pv[PF], pt[TPF], pc[CPF];
   if (pf) {
     const int ibw0 = min(ib, kref);
-    vstage_load<RW>(pv, V, ldv, vrows, kind, 0, ibw0, 0, ((ibw0 + 15) >> 4) * 16 * ROWS);
+    vstage_load<RW>(pv, V, ldv, vrows, 0, ibw0, 0, ((ibw0 + 15) >> 4) * 16 * ROWS);
     tstage_load(pt, T, ldt, ibw0);
     if (c1w) c1_load(pc, C1, ldc1, 0, ibw0, ncols, cg);
+  }
+  {
+    const int g = ln >> 4;
+    const bool cok = colok && gact;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rbase + rt * 16 + 4 * r + g;
+        c2[rt][r] = (cok && row < vrows) ? c2[rt][r] : 0.0;
+      }
   }
   const int nblk = (kref + ib - 1) / ib;
   for (int bi = 0; bi < nblk; ++bi) {
@@ -539,12 +569,11 @@ __device__ __forceinline__ void apply_strip(const Lds &L, const double *V, int64
       const int ng = min(L.gmax, nq - g0);
       __syncthreads();
       if (pf) {
-        vstage_store<RW>(L, pv, vrows, 0, nq * 16 * ROWS);
-        tstage_store(L, pt, ibp);
+        vstage_store<RW>(L, pv, vrows, kind, s, s + ibw, 0, nq * 16 * ROWS);
+        tstage_store(L, pt, ibp, ibw);
         if (sn < kref) {
           const int ibwn = min(ib, kref - sn);
-          vstage_load<RW>(pv, V, ldv, vrows, kind, sn, sn + ibwn, 0,
-                          ((ibwn + 15) >> 4) * 16 * ROWS);
+          vstage_load<RW>(pv, V, ldv, vrows, sn, sn + ibwn, 0, ((ibwn + 15) >> 4) * 16 * ROWS);
           tstage_load(pt, T + (int64_t)sn * ldt, ldt, ibwn);
         }
       } else {
@@ -552,7 +581,7 @@ __device__ __forceinline__ void apply_strip(const Lds &L, const double *V, int64
         if (g0 == 0 && tl) {
           double t[TPF];
           tstage_load(t, T + (int64_t)s * ldt, ldt, ibw);
-          tstage_store(L, t, ibp);
+          tstage_store(L, t, ibp, ibw);
         }
       }
       __syncthreads();
@@ -570,10 +599,11 @@ __device__ __forceinline__ void apply_strip(const Lds &L, const double *V, int64
 #pragma unroll
         for (int u = 0; u < CPF; ++u) {
           const int e = u * 64 + ln;
+          const double cv = colok ? pc[u] : 0.0;  // columns past ncols hold copies
           if (4 * u + 4 <= ibw)
-            yw[e] += pc[u];
+            yw[e] += cv;
           else if (4 * u < ibw && e < ibw * 16)
-            yw[e] += pc[u];
+            yw[e] += cv;
         }
       } else {
         c1_pass(yw, C1, ldc1, s, ibw, ncols, cg, true);

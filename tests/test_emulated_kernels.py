@@ -43,6 +43,8 @@ def _run(args, timeout=600):
     (150, 150, 136, 16),   # two row waves: LARFB/SSRFB with the register prefetch
     (280, 40, 256, 48),    # two row waves, T assembled over two register panels
     (520, 40, 512, 32),    # four row waves, T assembled over 16-column panels
+    (384, 320, 128, 16),   # full 128-row tiles and 64-column strips: the straight-line update
+    (384, 320, 128, 32),   # the same with two 16-column chunks per block
 ])
 def test_tile_qr_emulated(emu, M, N, nb, ib):
     out = _run([emu[0], str(M), str(N), str(nb), str(ib)])
