@@ -58,7 +58,11 @@ def tuned_vs_exhaustive(N, nb, ib):
     search's best at this size, from the tuner's recorded runs (None when the
     size was not searched exhaustively)."""
     import json
-    path = os.path.join(HERE, "paper_1102_5328_amd", "tuning", "tune_timings.json")
+    # the config-2 sweep taken with the current kernels; the tuner's own
+    # database otherwise
+    path = os.path.join(HERE, "paper_1102_5328_amd", "tuning", "sweep_timings.json")
+    if not os.path.exists(path):
+        path = os.path.join(HERE, "paper_1102_5328_amd", "tuning", "tune_timings.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
