@@ -54,9 +54,9 @@ def measured_traffic(N, nb, ib, units):
 
 
 def tuned_vs_exhaustive(N, nb, ib):
-    """GFLOP/s of the chosen (NB, IB) as a percentage of the exhaustive
-    search's best at this size, from the tuner's recorded runs (None when the
-    size was not searched exhaustively)."""
+    """GFLOP/s of the chosen (NB, IB) as a percentage of the best of all
+    39 pairs at this size, from the recorded config-2 sweep (None when the
+    size was not swept)."""
     import json
     # the config-2 sweep taken with the current kernels; the tuner's own
     # database otherwise
