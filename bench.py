@@ -100,12 +100,13 @@ def cpu_baseline(A_dev, target_s):
     import oracle
     M, N = A_dev.shape
     A = np.asfortranarray(A_dev.cpu().numpy())
-    # Calibrate on a copy: 2 steps.
-    probe = A[:, : min(N, 512)].copy(order="F")
+    # Calibrate on a full-width copy (a narrow one runs the OpenMP update at a
+    # lower rate and would overestimate the cost of a step): 8 steps.
+    probe = A.copy(order="F")
     t0 = time.perf_counter()
-    oracle.geqr2_steps_inplace(probe, 2)
-    t_probe = (time.perf_counter() - t0) * (N / probe.shape[1])  # scale to full width
-    per_step = max(t_probe / 2.0, 1e-4)
+    oracle.geqr2_steps_inplace(probe, 8)
+    per_step = max((time.perf_counter() - t0) / 8.0, 1e-4)
+    del probe
     steps = int(max(2, min(min(M, N), target_s / per_step)))
     t0 = time.perf_counter()
     oracle.geqr2_steps_inplace(A, steps)
